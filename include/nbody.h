@@ -1,0 +1,125 @@
+/*
+ * nbody.h - C ABI of libnbody.so: direct-sum softened gravity on AMD MI355X (gfx950).
+ *
+ * The library evaluates, for every i-particle,
+ *     a_i   =  sum_{j != i} m_j (x_j - x_i) / (|x_j - x_i|^2 + eps^2)^{3/2}
+ *     phi_i = -sum_{j != i} m_j / (|x_j - x_i|^2 + eps^2)^{1/2}
+ * (Hamada & Iitaka, Sec. 1.1, eq. (1); the potential is the quantity accumulated by
+ * the force-jerk-potential pipeline of Appendix A), with G = 1.  Pair arithmetic is
+ * FP32; accumulation is plain FP32, FP32 with FP64 per-tile reduction, or FP32
+ * with two-sum compensation (Sec. 2.2.2, eq. (2) is the paper's two-level form);
+ * the per-particle reduction of partial sums and the outputs are FP64.
+ *
+ * Conventions shared by every entry point
+ *   - Every array argument is a DEVICE pointer owned by the caller.  Positions are
+ *     structure-of-arrays: pos[0..n) holds x, pos[n..2n) y, pos[2n..3n) z ("[3][n]").
+ *     acc and grad_pos use the same [3][n] layout.  Arrays must be 4-byte aligned
+ *     (float) or 8-byte aligned (double).
+ *   - stream is a hipStream_t passed as void* (NULL = the null stream).  Every call
+ *     only enqueues work on it and returns without synchronising, except where a
+ *     function says otherwise.
+ *   - Outputs must not alias inputs.  n = 0 is a valid no-op.
+ *   - eps must be finite and > 0 (the self pair would otherwise be 0/0).
+ *   - NaN or Inf in the inputs propagate to the outputs; they are not checked.
+ *   - Scratch memory: if opts->workspace is NULL the library uses a per-device
+ *     buffer it allocates and grows on demand (calls on several streams of one
+ *     device that overlap in time then race; give each stream its own workspace).
+ *     While a stream is being captured into a HIP graph the library never
+ *     allocates: a missing or too small workspace returns NBODY_ECAPTURE.
+ *   - Errors: a negative status; nbody_last_error() returns a message for the
+ *     calling thread.  Invalid arguments are detected before anything is enqueued.
+ */
+#ifndef NBODY_H
+#define NBODY_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__) || defined(__clang__)
+#define NBODY_API __attribute__((visibility("default")))
+#else
+#define NBODY_API
+#endif
+
+typedef int32_t nbody_status;
+#define NBODY_OK 0
+#define NBODY_EINVAL (-1)      /* bad size, NULL pointer, eps, offsets or option   */
+#define NBODY_ENOMEM (-2)      /* device allocation failed                         */
+#define NBODY_EHIP (-3)        /* HIP runtime error (message has the HIP text)     */
+#define NBODY_ECAPTURE (-4)    /* would allocate while the stream is capturing     */
+#define NBODY_EUNSUPPORTED (-5)/* option combination not built                     */
+
+/* Accumulation of the pair terms of one i-particle (Sec. 2.2.2 and Sec. 3.4). */
+#define NBODY_PLAIN 0   /* one FP32 accumulator per j-segment; segments summed in FP32
+                           ("DIRECT style" when there is one segment)                  */
+#define NBODY_FP64RED 1 /* FP32 partial over each block of j, added into FP64 registers
+                           (the FORCE-LOOP of eq. (2) with an FP64 force memory)        */
+#define NBODY_COMP 2    /* FP32 partial over each block of j, added into an FP32
+                           (hi, lo) pair by an error-free two-sum; default              */
+
+/* Reference centre for FP64 positions (nbody_force_f64 and the leapfrog). */
+#define NBODY_CENTRE_NONE 0   /* pair arithmetic on fp32(x)                              */
+#define NBODY_CENTRE_SYSTEM 1 /* on fp32(x - c), c = FP64 mean position of the system;
+                                 default                                                 */
+#define NBODY_CENTRE_TILE 2   /* on fp32(x - c_I), c_I = FP64 mean of the i-tile, j's
+                                 converted for each i-tile as they are staged            */
+
+typedef struct nbody_opts {
+    int32_t precision;  /* NBODY_PLAIN, NBODY_FP64RED or NBODY_COMP                   */
+    int32_t centre;     /* NBODY_CENTRE_*; ignored by the FP32-position entry points  */
+    int32_t self_pot;   /* 0: phi excludes j == i (default); 1: phi includes -m_i/eps */
+    int32_t ipl;        /* i-particles per lane: 1, 2, 4, 8; 0 = tuned/default        */
+    int32_t jtile;      /* j-particles per LDS tile: 64, 128, 256, 512; 0 = default   */
+    int32_t nseg;       /* j-segments per i-tile (grid y); 0 = chosen from n          */
+    void *workspace;    /* device scratch, or NULL for the library's per-device cache */
+    size_t workspace_bytes;
+} nbody_opts;
+
+/* Fills *opts with the defaults (NBODY_COMP, NBODY_CENTRE_SYSTEM, self excluded,
+ * tile shape from the tuning table, library workspace). */
+NBODY_API void nbody_opts_default(nbody_opts *opts);
+
+/* Message of the last error on the calling thread ("" if none).  The pointer stays
+ * valid until the next library call on this thread. */
+NBODY_API const char *nbody_last_error(void);
+
+/* Library version string. */
+NBODY_API const char *nbody_version(void);
+
+/* Bytes of scratch that nbody_force*, nbody_force_vjp* and nbody_leapfrog* need for
+ * n particles with these options (the batched plan reports its own). */
+NBODY_API size_t nbody_workspace_size(int64_t n, const nbody_opts *opts);
+
+/* ------------------------------------------------------------------------------
+ * Forces and potentials, all i against all j of one system (eq. (1)).
+ *   n     particles, 0 <= n < 2^31
+ *   pos   float [3][n], positions (read)
+ *   mass  float [n], masses (read; any sign, zero allowed)
+ *   eps   softening length (> 0); the kernel uses fp32(eps * eps)
+ *   acc   double [3][n], accelerations (written)
+ *   pot   double [n] potentials (written), or NULL to skip them
+ * nbody_force uses the default options.  The j == i pair contributes nothing to
+ * acc (its separation is exactly zero) and its -m_i/eps is removed from phi in the
+ * FP64 reduction unless opts->self_pot is 1.
+ * ---------------------------------------------------------------------------- */
+NBODY_API nbody_status nbody_force(int64_t n, const float *pos, const float *mass, float eps,
+                         double *acc, double *pot, void *stream);
+NBODY_API nbody_status nbody_force_ex(int64_t n, const float *pos, const float *mass, float eps,
+                            double *acc, double *pot, const nbody_opts *opts, void *stream);
+
+/* As nbody_force_ex, with FP64 positions pos64 double [3][n].  The pair arithmetic
+ * stays FP32, on positions taken relative to the reference centre opts->centre
+ * (computed on the device in FP64).  This is the entry point for integrator state
+ * and for systems far from the origin. */
+NBODY_API nbody_status nbody_force_f64(int64_t n, const double *pos64, const float *mass, float eps,
+                             double *acc, double *pot, const nbody_opts *opts, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NBODY_H */

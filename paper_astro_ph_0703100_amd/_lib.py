@@ -1,0 +1,134 @@
+"""ctypes binding of ``libnbody.so`` with the C function names of ``include/nbody.h``.
+
+Argument marshalling only: every function here forwards plain integers, floats
+and device addresses to the C ABI and returns its status.  The library is loaded
+on first use; if it has not been built this raises (there is no fallback).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libnbody.so")
+
+NBODY_OK = 0
+NBODY_EINVAL = -1
+NBODY_ENOMEM = -2
+NBODY_EHIP = -3
+NBODY_ECAPTURE = -4
+NBODY_EUNSUPPORTED = -5
+
+NBODY_PLAIN = 0
+NBODY_FP64RED = 1
+NBODY_COMP = 2
+
+NBODY_CENTRE_NONE = 0
+NBODY_CENTRE_SYSTEM = 1
+NBODY_CENTRE_TILE = 2
+
+PRECISIONS = {"plain": NBODY_PLAIN, "fp64red": NBODY_FP64RED, "comp": NBODY_COMP}
+CENTRES = {"none": NBODY_CENTRE_NONE, "system": NBODY_CENTRE_SYSTEM, "tile": NBODY_CENTRE_TILE}
+
+
+class nbody_opts(ctypes.Structure):
+    _fields_ = [
+        ("precision", ctypes.c_int32),
+        ("centre", ctypes.c_int32),
+        ("self_pot", ctypes.c_int32),
+        ("ipl", ctypes.c_int32),
+        ("jtile", ctypes.c_int32),
+        ("nseg", ctypes.c_int32),
+        ("workspace", ctypes.c_void_p),
+        ("workspace_bytes", ctypes.c_size_t),
+    ]
+
+
+class NBodyError(RuntimeError):
+    """A negative status from the library, with its message."""
+
+    def __init__(self, status: int, func: str, msg: str):
+        super().__init__("%s failed (status %d): %s" % (func, status, msg))
+        self.status = status
+
+
+_lock = threading.Lock()
+_lib = None
+
+_I64 = ctypes.c_int64
+_I32 = ctypes.c_int32
+_P = ctypes.c_void_p
+_F = ctypes.c_float
+_D = ctypes.c_double
+_OPTS = ctypes.POINTER(nbody_opts)
+
+# name -> (restype, argtypes); every symbol include/nbody.h declares.
+SIGNATURES = {
+    "nbody_opts_default": (None, [_OPTS]),
+    "nbody_last_error": (ctypes.c_char_p, []),
+    "nbody_version": (ctypes.c_char_p, []),
+    "nbody_workspace_size": (ctypes.c_size_t, [_I64, _OPTS]),
+    "nbody_force": (_I32, [_I64, _P, _P, _F, _P, _P, _P]),
+    "nbody_force_ex": (_I32, [_I64, _P, _P, _F, _P, _P, _OPTS, _P]),
+    "nbody_force_f64": (_I32, [_I64, _P, _P, _F, _P, _P, _OPTS, _P]),
+}
+
+
+def load():
+    """Load ``libnbody.so`` (built in-tree) and declare its functions."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError(
+                    "libnbody.so is not built (%s); run python -m paper_astro_ph_0703100_amd.build"
+                    % LIB_PATH)
+            lib = ctypes.CDLL(LIB_PATH)
+            for name, (res, args) in SIGNATURES.items():
+                f = getattr(lib, name)
+                f.restype = res
+                f.argtypes = args
+            _lib = lib
+    return _lib
+
+
+def _check(status: int, func: str) -> int:
+    if status != NBODY_OK:
+        raise NBodyError(status, func, nbody_last_error())
+    return status
+
+
+def nbody_last_error() -> str:
+    return load().nbody_last_error().decode()
+
+
+def nbody_version() -> str:
+    return load().nbody_version().decode()
+
+
+def nbody_opts_default() -> nbody_opts:
+    o = nbody_opts()
+    load().nbody_opts_default(ctypes.byref(o))
+    return o
+
+
+def nbody_workspace_size(n: int, opts: nbody_opts | None) -> int:
+    return int(load().nbody_workspace_size(n, ctypes.byref(opts) if opts is not None else None))
+
+
+def nbody_force(n, pos, mass, eps, acc, pot, stream, check=True):
+    st = load().nbody_force(n, pos, mass, eps, acc, pot, stream)
+    return _check(st, "nbody_force") if check else st
+
+
+def nbody_force_ex(n, pos, mass, eps, acc, pot, opts, stream, check=True):
+    st = load().nbody_force_ex(n, pos, mass, eps, acc, pot,
+                               ctypes.byref(opts) if opts is not None else None, stream)
+    return _check(st, "nbody_force_ex") if check else st
+
+
+def nbody_force_f64(n, pos64, mass, eps, acc, pot, opts, stream, check=True):
+    st = load().nbody_force_f64(n, pos64, mass, eps, acc, pot,
+                                ctypes.byref(opts) if opts is not None else None, stream)
+    return _check(st, "nbody_force_f64") if check else st

@@ -1,0 +1,276 @@
+// Host side of the C ABI: argument validation, launch-shape choice, scratch memory
+// and dispatch to the kernels.  Nothing here touches particle data on the host.
+#include <cfloat>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <string>
+
+#include "nbody_internal.h"
+#include "tuning.h"
+
+namespace nbody {
+
+namespace {
+thread_local std::string g_error;
+
+constexpr int kMaxDevices = 64;
+struct Workspace {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+std::mutex g_ws_mu;
+Workspace g_ws[kMaxDevices];
+
+std::mutex g_dev_mu;
+bool g_dev_ready[kMaxDevices];
+DeviceInfo g_dev[kMaxDevices];
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+}  // namespace
+
+nbody_status set_error(nbody_status code, const std::string &msg) {
+    g_error = msg;
+    return code;
+}
+
+nbody_status hip_error(hipError_t e, const char *what) {
+    g_error = std::string(what) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? NBODY_ENOMEM : NBODY_EHIP;
+}
+
+void clear_error() { g_error.clear(); }
+
+const DeviceInfo &device_info() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) dev = 0;
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    if (!g_dev_ready[dev]) {
+        hipDeviceProp_t p;
+        if (hipGetDeviceProperties(&p, dev) == hipSuccess) {
+            g_dev[dev].cus = p.multiProcessorCount > 0 ? p.multiProcessorCount : 256;
+            g_dev[dev].warp = p.warpSize;
+        }
+        g_dev_ready[dev] = true;
+    }
+    return g_dev[dev];
+}
+
+bool stream_capturing(hipStream_t s) {
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &st) != hipSuccess) return false;
+    return st != hipStreamCaptureStatusNone;
+}
+
+// Scratch of at least `need` bytes: the caller's buffer, or the per-device cache
+// (grown outside stream capture only).
+nbody_status get_workspace(const nbody_opts &o, size_t need, hipStream_t s, void **out) {
+    if (need == 0) {
+        *out = o.workspace;
+        return NBODY_OK;
+    }
+    if (o.workspace) {
+        if (o.workspace_bytes < need)
+            return set_error(NBODY_EINVAL, "workspace too small: need " + std::to_string(need) +
+                                               " bytes, got " + std::to_string(o.workspace_bytes));
+        if (reinterpret_cast<uintptr_t>(o.workspace) % 256)
+            return set_error(NBODY_EINVAL, "workspace must be 256-byte aligned");
+        *out = o.workspace;
+        return NBODY_OK;
+    }
+    int dev = 0;
+    NBODY_HIP_CHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return set_error(NBODY_EINVAL, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    Workspace &w = g_ws[dev];
+    if (w.bytes >= need) {
+        *out = w.ptr;
+        return NBODY_OK;
+    }
+    if (stream_capturing(s))
+        return set_error(NBODY_ECAPTURE,
+                         "stream is capturing and the library workspace is too small; pass "
+                         "opts->workspace (nbody_workspace_size bytes)");
+    if (w.ptr) {
+        // hipFree waits for the device, so no kernel still uses the old buffer.
+        NBODY_HIP_CHECK(hipFree(w.ptr));
+        w.ptr = nullptr;
+        w.bytes = 0;
+    }
+    const size_t bytes = align_up(need + need / 4, 1 << 20);
+    hipError_t e = hipMalloc(&w.ptr, bytes);
+    if (e != hipSuccess) {
+        w.ptr = nullptr;
+        return hip_error(e, "hipMalloc(workspace)");
+    }
+    w.bytes = bytes;
+    *out = w.ptr;
+    return NBODY_OK;
+}
+
+// Launch shape for n particles: explicit options first, then the tuning table, then
+// a default that gives every compute unit several blocks.
+nbody_status choose_cfg(int64_t n, int precision, const nbody_opts &o, TileCfg *cfg) {
+    TileCfg c;
+    TuneEntry t = tuned_shape(KERNEL_FORCE, precision, n);
+    c.ipl = o.ipl ? o.ipl : t.ipl;
+    c.jt = o.jtile ? o.jtile : t.jt;
+    if (!(c.ipl == 1 || c.ipl == 2 || c.ipl == 4 || c.ipl == 8))
+        return set_error(NBODY_EINVAL, "ipl must be 1, 2, 4 or 8");
+    if (!(c.jt == 64 || c.jt == 128 || c.jt == 256 || c.jt == 512))
+        return set_error(NBODY_EINVAL, "jtile must be 64, 128, 256 or 512");
+    if (o.nseg < 0 || o.nseg > kMaxSeg)
+        return set_error(NBODY_EINVAL, "nseg must be in [0, " + std::to_string(kMaxSeg) + "]");
+    const int64_t itile = (int64_t)kTPB * c.ipl;
+    c.itiles = (int)((n + itile - 1) / itile);
+    c.npad = (int)(c.itiles * itile);
+    const int64_t jtiles = (n + c.jt - 1) / c.jt;
+    int64_t nseg = o.nseg ? o.nseg : t.nseg;
+    if (nseg <= 0) {
+        const int64_t target = (int64_t)device_info().cus * 8;
+        nseg = (target + c.itiles - 1) / c.itiles;
+        const int64_t cap = jtiles / 4 > 1 ? jtiles / 4 : 1;  // at least 4 tiles per segment
+        if (nseg > cap) nseg = cap;
+    }
+    if (nseg > jtiles) nseg = jtiles > 0 ? jtiles : 1;
+    if (nseg > kMaxSeg) nseg = kMaxSeg;
+    if (nseg < 1) nseg = 1;
+    const int64_t per = (jtiles + nseg - 1) / nseg;  // tiles per segment
+    c.seg_len = (int)(per * c.jt);
+    c.nseg = (int)((jtiles + per - 1) / per);
+    if (c.nseg < 1) c.nseg = 1;
+    *cfg = c;
+    return NBODY_OK;
+}
+
+size_t partial_bytes(const TileCfg &c, int precision) {
+    return align_up((size_t)c.nseg * partial_words(precision) * (size_t)c.npad * 4, 256);
+}
+
+}  // namespace nbody
+
+using namespace nbody;
+
+namespace {
+
+nbody_status check_common(int64_t n, const void *pos, const void *mass, float eps,
+                          const void *acc, const nbody_opts &o) {
+    if (n < 0 || n > INT32_MAX / 2) return set_error(NBODY_EINVAL, "n must be in [0, 2^30)");
+    if (n > 0 && (!pos || !mass || !acc))
+        return set_error(NBODY_EINVAL, "pos, mass and acc must not be NULL");
+    const float e2 = eps * eps;
+    if (!std::isfinite(eps) || !(eps > 0.0f) || !(e2 >= FLT_MIN) || !std::isfinite(e2))
+        return set_error(NBODY_EINVAL, "eps must be finite and > 0 with eps^2 a normal float");
+    if (o.precision < NBODY_PLAIN || o.precision > NBODY_COMP)
+        return set_error(NBODY_EINVAL, "precision must be NBODY_PLAIN, NBODY_FP64RED or NBODY_COMP");
+    if (o.self_pot != 0 && o.self_pot != 1) return set_error(NBODY_EINVAL, "self_pot must be 0 or 1");
+    if (o.centre < NBODY_CENTRE_NONE || o.centre > NBODY_CENTRE_TILE)
+        return set_error(NBODY_EINVAL, "centre must be NBODY_CENTRE_NONE, _SYSTEM or _TILE");
+    return NBODY_OK;
+}
+
+template <typename T>
+bool misaligned(const T *p) {
+    return reinterpret_cast<uintptr_t>(p) % alignof(T) != 0;
+}
+
+// Pair kernel + FP64 reduction on FP32 structure-of-arrays positions.
+nbody_status force_f32_core(int64_t n, const float *pos, const float *mass, float eps, double *acc,
+                            double *pot, const nbody_opts &o, const TileCfg &cfg, void *ws,
+                            hipStream_t s) {
+    const float e2 = eps * eps;
+    PairArgs pa{pos, pos + n, pos + 2 * n, mass, (int)n, cfg.seg_len, e2, ws, cfg.npad};
+    nbody_status st = launch_pair(cfg, o.precision, pot != nullptr, pa, s);
+    if (st) return st;
+    FinalizeArgs fa{ws, cfg.nseg, cfg.npad, (int)n, mass, e2, o.self_pot, acc, pot};
+    return launch_finalize(o.precision, fa, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+void nbody_opts_default(nbody_opts *opts) {
+    if (!opts) return;
+    std::memset(opts, 0, sizeof(*opts));
+    opts->precision = NBODY_COMP;
+    opts->centre = NBODY_CENTRE_SYSTEM;
+    opts->self_pot = 0;
+}
+
+const char *nbody_last_error(void) { return g_error.c_str(); }
+
+const char *nbody_version(void) { return "nbody-gfx950 0.1"; }
+
+size_t nbody_workspace_size(int64_t n, const nbody_opts *opts) {
+    nbody_opts o;
+    nbody_opts_default(&o);
+    if (opts) o = *opts;
+    if (n <= 0) return 0;
+    TileCfg c;
+    if (choose_cfg(n, o.precision, o, &c) != NBODY_OK) return 0;
+    size_t b = partial_bytes(c, o.precision);
+    b += align_up(sizeof(float) * 3 * (size_t)n, 256);  // FP32 relative positions
+    b += align_up(centre_scratch_bytes() + 4 * sizeof(double), 256);
+    return b;
+}
+
+nbody_status nbody_force_ex(int64_t n, const float *pos, const float *mass, float eps, double *acc,
+                            double *pot, const nbody_opts *opts, void *stream) {
+    clear_error();
+    nbody_opts o;
+    nbody_opts_default(&o);
+    if (opts) o = *opts;
+    nbody_status st = check_common(n, pos, mass, eps, acc, o);
+    if (st) return st;
+    if (misaligned(pos) || misaligned(mass) || misaligned(acc) || misaligned(pot))
+        return set_error(NBODY_EINVAL, "misaligned array argument");
+    if (n == 0) return NBODY_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    TileCfg cfg;
+    if ((st = choose_cfg(n, o.precision, o, &cfg))) return st;
+    void *ws = nullptr;
+    if ((st = get_workspace(o, partial_bytes(cfg, o.precision), s, &ws))) return st;
+    return force_f32_core(n, pos, mass, eps, acc, pot, o, cfg, ws, s);
+}
+
+nbody_status nbody_force(int64_t n, const float *pos, const float *mass, float eps, double *acc,
+                         double *pot, void *stream) {
+    return nbody_force_ex(n, pos, mass, eps, acc, pot, nullptr, stream);
+}
+
+nbody_status nbody_force_f64(int64_t n, const double *pos64, const float *mass, float eps,
+                             double *acc, double *pot, const nbody_opts *opts, void *stream) {
+    clear_error();
+    nbody_opts o;
+    nbody_opts_default(&o);
+    if (opts) o = *opts;
+    nbody_status st = check_common(n, pos64, mass, eps, acc, o);
+    if (st) return st;
+    if (misaligned(pos64) || misaligned(mass) || misaligned(acc) || misaligned(pot))
+        return set_error(NBODY_EINVAL, "misaligned array argument");
+    if (o.centre == NBODY_CENTRE_TILE)
+        return set_error(NBODY_EUNSUPPORTED, "NBODY_CENTRE_TILE is not available");
+    if (n == 0) return NBODY_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    TileCfg cfg;
+    if ((st = choose_cfg(n, o.precision, o, &cfg))) return st;
+    const size_t pb = partial_bytes(cfg, o.precision);
+    const size_t xb = align_up(sizeof(float) * 3 * (size_t)n, 256);
+    const size_t cb = align_up(centre_scratch_bytes() + 4 * sizeof(double), 256);
+    void *ws = nullptr;
+    if ((st = get_workspace(o, pb + xb + cb, s, &ws))) return st;
+    char *base = static_cast<char *>(ws);
+    float *x32 = reinterpret_cast<float *>(base + pb);
+    double *cen = reinterpret_cast<double *>(base + pb + xb);
+    double *cscr = cen + 4;
+    if (o.centre == NBODY_CENTRE_SYSTEM) {
+        if ((st = launch_centre(n, pos64, cen, cscr, s))) return st;
+        if ((st = launch_convert(n, pos64, cen, x32, s))) return st;
+    } else {
+        if ((st = launch_convert(n, pos64, nullptr, x32, s))) return st;
+    }
+    return force_f32_core(n, x32, mass, eps, acc, pot, o, cfg, ws, s);
+}
+
+}  // extern "C"

@@ -1,0 +1,23 @@
+// Launch-shape table: built-in defaults, optionally overridden by a JSON file
+// written by the autotuner (nbody_tune_load / nbody_tune_save).
+#pragma once
+
+#include <cstdint>
+
+namespace nbody {
+
+enum TuneKernel { KERNEL_FORCE = 0, KERNEL_VJP = 1, KERNEL_BATCHED = 2, KERNEL_COUNT = 3 };
+
+struct TuneEntry {
+    int ipl;   // i-particles per lane
+    int jt;    // j-tile
+    int nseg;  // j-segments, 0 = chosen from n
+};
+
+// Shape for a kernel, precision mode and problem size (size bucket = floor(log2 n)).
+TuneEntry tuned_shape(int kernel, int precision, int64_t n);
+
+// Replace the entry for (kernel, precision, size bucket of n).
+void set_tuned_shape(int kernel, int precision, int64_t n, const TuneEntry &e);
+
+}  // namespace nbody
