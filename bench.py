@@ -1,18 +1,23 @@
 #!/usr/bin/env python3
-"""Throughput of the direct-sum force path on one MI355X, with accuracy and roofline.
+"""Throughput of the direct-sum gravity path on one MI355X, with accuracy and roofline.
 
-Workload (default): N = 131072 equal-mass Plummer sphere (scale 1, total mass 1,
-truncated at 20 scale radii, distribution-function velocities), eps = 0.4 / N^{1/3},
-FP32 structure-of-arrays positions and masses, seed 2.
+Workload (default ``plummer_131072``): N = 131072 equal-mass Plummer sphere (scale 1,
+total mass 1, truncated at 20 scale radii, distribution-function velocities), seed 2,
+eps = 0.4 / N^{1/3}, FP32 masses, FP64 positions and velocities.
 
-A step is one force + potential evaluation of all N particles (N^2 pair
-interactions) with compensated FP32 accumulation and FP64 reduction.  The same
-number of steps is timed with plain FP32 accumulation.  ``value`` is pair
-interactions per second of the compensated path with inputs resident in HBM.
+A step is one kick-drift-kick leapfrog step (dt = 1/256) replayed from a HIP graph:
+first kick + drift (FP64), FP64 centre, FP32 conversion, pair kernel (N^2 pair
+interactions, compensated FP32 accumulation), FP64 reduction fused with the second
+kick.  ``value`` is N^2 * steps / wall time (pair interactions per second, inputs
+resident in HBM).  The same is timed with plain FP32 accumulation.
 
-Accuracy: the CPU-baseline leg runs the FP64 oracle on the same particles (all N
-i-particles, i.e. one full evaluation); its result gives the relative RMS and
-maximum (eq. (3)) errors of every mode, and its wall time gives the CPU rate.
+Roofline: the pair kernel (plus its FP64 finalize) is timed with HIP events around
+standalone force evaluations on the same stream, and compared with the issue limit
+of 17 VALU slots per pair.
+
+Accuracy: the CPU-baseline leg runs the FP64 oracle on the initial positions (all N
+i-particles by default); its result gives the relative RMS and maximum (eq. (3))
+errors of each mode's force evaluation, and its wall time the CPU rate.
 
 Prints one JSON line.  ``--gpus`` above 1 is refused: the path runs on one GPU.
 """
@@ -58,6 +63,7 @@ def parse():
                     help="skip the FP64 oracle leg (no errors, no CPU rate)")
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="i-particles the oracle evaluates (0 = all N)")
+    ap.add_argument("--modes", default="comp,plain,fp64red")
     return ap.parse_args()
 
 
@@ -65,7 +71,8 @@ def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py: this path runs on one GPU; --gpus %d is not supported "
-              "(the multi-GPU sharding is described, not built)" % args.gpus, file=sys.stderr)
+              "(the multi-GPU sharding is described in DESIGN.md, not built)" % args.gpus,
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -74,52 +81,77 @@ def main():
 
     w = ics.WORKLOADS[args.workload]
     n = w.n
-    pos, _vel, mass = ics.plummer(n, seed=w.seed)
-    p32 = np.ascontiguousarray(pos.T.astype(np.float32))
+    dt = w.dt or 1.0 / 256
+    pos, vel, mass = ics.plummer(n, seed=w.seed)
     m32 = mass.astype(np.float32)
     eps = float(np.float32(w.eps))
     dev = torch.device("cuda:0")
-    p = torch.from_numpy(p32).to(dev)
+    x0 = torch.from_numpy(np.ascontiguousarray(pos.T)).to(dev)
+    v0 = torch.from_numpy(np.ascontiguousarray(vel.T)).to(dev)
     m = torch.from_numpy(m32).to(dev)
-    acc = torch.empty((3, n), dtype=torch.float64, device=dev)
-    pot = torch.empty(n, dtype=torch.float64, device=dev)
+    p32 = torch.from_numpy(np.ascontiguousarray(pos.T.astype(np.float32))).to(dev)
     stream = torch.cuda.current_stream()
     sp = stream.cuda_stream
     pairs = float(n) * float(n)
+    modes = [s for s in args.modes.split(",") if s]
 
-    def run_mode(precision: str, steps: int, warmup: int):
-        opts = api.make_opts(precision=precision)
-        for _ in range(warmup):
-            _lib.nbody_force_ex(n, p.data_ptr(), m.data_ptr(), eps, acc.data_ptr(), pot.data_ptr(),
-                                opts, sp)
+    def timed_steps(precision: str):
+        """K graph-replayed KDK steps from the initial state; wall time and per-step ms."""
+        x, v = x0.clone(), v0.clone()
+        acc, _, _ = api.leapfrog(x, v, m, eps, dt, 0, precision=precision)
+        g = api.LeapfrogGraph(x, v, m, eps, dt, 1, acc, precision=precision)
+        for _ in range(args.warmup):
+            g.launch()
+        torch.cuda.synchronize()
+        x.copy_(x0)
+        v.copy_(v0)
+        api.leapfrog(x, v, m, eps, dt, 0, acc=acc, precision=precision)
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in range(steps)]
+              for _ in range(args.steps)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for k in range(steps):
+        for k in range(args.steps):
             ev[k][0].record(stream)
-            _lib.nbody_force_ex(n, p.data_ptr(), m.data_ptr(), eps, acc.data_ptr(), pot.data_ptr(),
-                                opts, sp)
+            g.launch()
             ev[k][1].record(stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        kms = [a.elapsed_time(b) for a, b in ev]
-        return wall, kms, acc.cpu().numpy().T.copy(), pot.cpu().numpy().copy()
+        g.close()
+        return wall, [a.elapsed_time(b) for a, b in ev]
+
+    def timed_force(precision: str, reps: int):
+        """Events around standalone force evaluations (pair kernel + FP64 finalize)."""
+        acc = torch.empty((3, n), dtype=torch.float64, device=dev)
+        pot = torch.empty(n, dtype=torch.float64, device=dev)
+        opts = api.make_opts(precision=precision)
+        call = lambda: _lib.nbody_force_ex(n, p32.data_ptr(), m.data_ptr(), eps, acc.data_ptr(),
+                                           pot.data_ptr(), opts, sp)
+        call()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(reps)]
+        torch.cuda.synchronize()
+        for k in range(reps):
+            ev[k][0].record(stream)
+            call()
+            ev[k][1].record(stream)
+        torch.cuda.synchronize()
+        return [a.elapsed_time(b) for a, b in ev]
+
+    def force_f64(precision: str):
+        acc, pot = api.force_f64(x0, m, eps, precision=precision)
+        torch.cuda.synchronize()
+        return acc.cpu().numpy().T.copy(), pot.cpu().numpy().copy()
 
     res = {}
-    for precision in ("comp", "plain", "fp64red"):
-        steps = args.steps if precision != "fp64red" else max(1, min(args.steps, 2))
-        wall, kms, a_np, p_np = run_mode(precision, steps, args.warmup)
-        res[precision] = {"wall": wall, "steps": steps, "kernel_ms": float(np.mean(kms)),
-                          "kernel_ms_min": float(np.min(kms)), "acc": a_np, "pot": p_np}
-        print("bench: %-8s %d steps  %.3f ms/step  kernel %.3f ms" %
-              (precision, steps, wall / steps * 1e3, np.mean(kms)), file=sys.stderr, flush=True)
-
-    comp = res["comp"]
-    value = pairs * comp["steps"] / comp["wall"]
-    k_ms = comp["kernel_ms"]
-    achieved_tf = pairs * FLOPS_PER_PAIR / (k_ms * 1e-3) / 1e12
-    peak_tf = peak_pairs_per_s() * FLOPS_PER_PAIR / 1e12
+    for precision in modes:
+        wall, step_ms = timed_steps(precision)
+        kms = timed_force(precision, max(args.steps, 3))
+        a_np, p_np = force_f64(precision)
+        res[precision] = {"wall": wall, "step_ms": step_ms, "kernel_ms": float(np.mean(kms)),
+                          "acc": a_np, "pot": p_np}
+        print("bench: %-8s %d steps  %.3f ms/step (wall)  force kernel %.3f ms" %
+              (precision, args.steps, wall / args.steps * 1e3, np.mean(kms)),
+              file=sys.stderr, flush=True)
 
     cpu = None
     errors = {}
@@ -127,14 +159,13 @@ def main():
         import oracle
         k = n if args.cpu_sample <= 0 else min(n, args.cpu_sample)
         idx = np.arange(n) if k == n else ics.sample_indices(n, k, seed=w.seed + 1000)
-        x64 = p32.T.astype(np.float64)
         t0 = time.perf_counter()
-        ra, rp = oracle.force_sampled(x64, m32.astype(np.float64), eps, idx)
+        ra, rp = oracle.force_sampled(pos, m32.astype(np.float64), eps, idx)
         ct = time.perf_counter() - t0
         cpu = {"value": k * float(n) / ct, "unit": "pair-interactions/s",
                "cores": oracle.threads(), "kind": "oracle",
-               "sample": "%d i-particles x %d j-particles of the same sphere, FP64, one "
-                         "force+potential evaluation (%.1f s)" % (k, n, ct)}
+               "sample": "force+potential of %d i-particles from all %d particles of the same "
+                         "sphere at the initial positions, FP64 (%.1f s)" % (k, n, ct)}
         for precision, r in res.items():
             ea = metrics.rel_errors(r["acc"][idx], ra)
             ep = metrics.rel_errors(r["pot"][idx], rp)
@@ -142,34 +173,42 @@ def main():
                                  "acc_normwise": ea["normwise"], "pot_rel_rms": ep["rel_rms"],
                                  "pot_e_max": ep["e_max"], "sample": int(idx.size)}
 
-    plain = res["plain"]
+    head = modes[0]
+    r0 = res[head]
+    k_ms = r0["kernel_ms"]
+    achieved_tf = pairs * FLOPS_PER_PAIR / (k_ms * 1e-3) / 1e12
+    peak_tf = peak_pairs_per_s() * FLOPS_PER_PAIR / 1e12
     line = {
         "metric": METRIC,
-        "value": value,
+        "value": pairs * args.steps / r0["wall"],
         "unit": "pair-interactions/s",
         "n_gpus": 1,
-        "steps": comp["steps"],
+        "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": comp["wall"] / comp["steps"] * 1e3,
+        "ms_per_step": r0["wall"] / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": w.name, "n": n, "eps": eps, "seed": w.seed,
-                   "precision": "comp", "step": "one force+potential evaluation (N^2 pairs)",
+        "config": {"workload": w.name, "n": n, "eps": eps, "seed": w.seed, "dt": dt,
+                   "precision": head,
+                   "step": "one graph-replayed KDK leapfrog step: FP64 state, FP32 pair "
+                           "arithmetic relative to the system centre, one N^2 force evaluation",
                    "description": w.description},
         "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": peak_tf, "unit": "TFLOP/s",
                      "frac": achieved_tf / peak_tf, "traffic": None,
-                     "kernel": "pair_kernel + finalize", "kernel_ms": k_ms,
+                     "kernel": "pair_kernel (+ finalize_kernel, <0.3%)", "kernel_ms": k_ms,
                      "flops_per_pair": FLOPS_PER_PAIR,
-                     "issue_slots_per_pair": VALU_PER_PAIR + RSQ_SLOTS},
+                     "issue_slots_per_pair": VALU_PER_PAIR + RSQ_SLOTS,
+                     "peak_pairs_per_s": peak_pairs_per_s()},
         "cpu_baseline": cpu,
-        "plain": {"value": pairs * plain["steps"] / plain["wall"],
-                  "ms_per_step": plain["wall"] / plain["steps"] * 1e3,
-                  "kernel_ms": plain["kernel_ms"]},
-        "fp64red": {"kernel_ms": res["fp64red"]["kernel_ms"]},
-        "errors": errors,
+        "modes": {p: {"value": pairs * args.steps / r["wall"],
+                      "ms_per_step": r["wall"] / args.steps * 1e3,
+                      "step_ms_events": float(np.mean(r["step_ms"])),
+                      "force_kernel_ms": r["kernel_ms"],
+                      "roofline_frac": pairs / (r["kernel_ms"] * 1e-3) / peak_pairs_per_s(),
+                      "errors": errors.get(p)} for p, r in res.items()},
         "gflops_38": metrics.gflops(pairs, k_ms * 1e-3, 38),
         "gflops_20": metrics.gflops(pairs, k_ms * 1e-3, 20),
     }

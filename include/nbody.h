@@ -118,6 +118,39 @@ NBODY_API nbody_status nbody_force_ex(int64_t n, const float *pos, const float *
 NBODY_API nbody_status nbody_force_f64(int64_t n, const double *pos64, const float *mass, float eps,
                              double *acc, double *pot, const nbody_opts *opts, void *stream);
 
+/* ------------------------------------------------------------------------------
+ * Kick-drift-kick leapfrog on FP64 state (the paper has no integrator; this is the
+ * standard second-order symplectic scheme).  One step:
+ *     v += (dt/2) a(x);   x += dt v;   a = a(x);   v += (dt/2) a
+ * with a(x) from nbody_force_f64 (same options; opts->centre applies).
+ *   pos64, vel64  double [3][n], updated in place
+ *   acc           double [3][n]: on entry a(pos64) unless flags has
+ *                 NBODY_LF_INIT_ACC (then it is computed first); on exit a(final pos)
+ *   pot           double [n] potentials at the final positions, or NULL
+ *   traj          double [nsteps+1][3][n] position checkpoints x_0 .. x_nsteps, or
+ *                 NULL (these are the states the adjoint needs)
+ *   nsteps >= 0, dt finite (negative dt integrates backwards).
+ * ---------------------------------------------------------------------------- */
+#define NBODY_LF_INIT_ACC 1
+NBODY_API nbody_status nbody_leapfrog(int64_t n, double *pos64, double *vel64, const float *mass,
+                                      float eps, double dt, int32_t nsteps, double *acc,
+                                      double *pot, double *traj, int32_t flags,
+                                      const nbody_opts *opts, void *stream);
+
+/* HIP graph of nsteps leapfrog steps (as nbody_leapfrog without NBODY_LF_INIT_ACC and
+ * without checkpoints) on fixed arrays: every nbody_graph_launch replays the steps on
+ * the device with no host work per kernel.  The graph owns its own scratch memory
+ * (allocated here, outside any capture); the arrays passed here must stay valid for
+ * the graph's lifetime.  nbody_graph_destroy waits for the device first. */
+typedef struct nbody_graph nbody_graph;
+NBODY_API nbody_status nbody_graph_create_leapfrog(int64_t n, double *pos64, double *vel64,
+                                                   const float *mass, float eps, double dt,
+                                                   int32_t nsteps, double *acc, double *pot,
+                                                   const nbody_opts *opts, void *stream,
+                                                   nbody_graph **out);
+NBODY_API nbody_status nbody_graph_launch(nbody_graph *graph, void *stream);
+NBODY_API void nbody_graph_destroy(nbody_graph *graph);
+
 #ifdef __cplusplus
 }
 #endif

@@ -72,7 +72,14 @@ SIGNATURES = {
     "nbody_force": (_I32, [_I64, _P, _P, _F, _P, _P, _P]),
     "nbody_force_ex": (_I32, [_I64, _P, _P, _F, _P, _P, _OPTS, _P]),
     "nbody_force_f64": (_I32, [_I64, _P, _P, _F, _P, _P, _OPTS, _P]),
+    "nbody_leapfrog": (_I32, [_I64, _P, _P, _P, _F, _D, _I32, _P, _P, _P, _I32, _OPTS, _P]),
+    "nbody_graph_create_leapfrog": (_I32, [_I64, _P, _P, _P, _F, _D, _I32, _P, _P, _OPTS, _P,
+                                           ctypes.POINTER(_P)]),
+    "nbody_graph_launch": (_I32, [_P, _P]),
+    "nbody_graph_destroy": (None, [_P]),
 }
+
+NBODY_LF_INIT_ACC = 1
 
 
 def load():
@@ -132,3 +139,32 @@ def nbody_force_f64(n, pos64, mass, eps, acc, pot, opts, stream, check=True):
     st = load().nbody_force_f64(n, pos64, mass, eps, acc, pot,
                                 ctypes.byref(opts) if opts is not None else None, stream)
     return _check(st, "nbody_force_f64") if check else st
+
+
+def _opt_ref(opts):
+    return ctypes.byref(opts) if opts is not None else None
+
+
+def nbody_leapfrog(n, pos64, vel64, mass, eps, dt, nsteps, acc, pot, traj, flags, opts, stream,
+                   check=True):
+    st = load().nbody_leapfrog(n, pos64, vel64, mass, eps, dt, nsteps, acc, pot, traj, flags,
+                               _opt_ref(opts), stream)
+    return _check(st, "nbody_leapfrog") if check else st
+
+
+def nbody_graph_create_leapfrog(n, pos64, vel64, mass, eps, dt, nsteps, acc, pot, opts, stream):
+    """Returns the graph handle (an integer address)."""
+    h = ctypes.c_void_p()
+    st = load().nbody_graph_create_leapfrog(n, pos64, vel64, mass, eps, dt, nsteps, acc, pot,
+                                            _opt_ref(opts), stream, ctypes.byref(h))
+    _check(st, "nbody_graph_create_leapfrog")
+    return h.value
+
+
+def nbody_graph_launch(graph, stream, check=True):
+    st = load().nbody_graph_launch(graph, stream)
+    return _check(st, "nbody_graph_launch") if check else st
+
+
+def nbody_graph_destroy(graph):
+    load().nbody_graph_destroy(graph)

@@ -11,7 +11,8 @@ import torch
 
 from . import _lib
 
-__all__ = ["make_opts", "force", "force_f64", "soa", "aos", "stream_ptr"]
+__all__ = ["make_opts", "force", "force_f64", "leapfrog", "LeapfrogGraph", "soa", "aos",
+           "stream_ptr"]
 
 
 def make_opts(precision: str = "comp", centre: str = "system", self_pot: bool = False,
@@ -81,3 +82,68 @@ def force_f64(pos64: torch.Tensor, mass: torch.Tensor, eps: float, precision: st
     _lib.nbody_force_f64(n, pos64.data_ptr(), mass.data_ptr(), float(eps), acc.data_ptr(),
                          pot.data_ptr() if pot is not None else None, opts, stream_ptr())
     return acc, pot
+
+
+def leapfrog(pos64: torch.Tensor, vel64: torch.Tensor, mass: torch.Tensor, eps: float, dt: float,
+             nsteps: int, acc: torch.Tensor | None = None, init: bool = True,
+             with_pot: bool = False, keep_trajectory: bool = False, precision: str = "comp",
+             centre: str = "system", **kw):
+    """``nsteps`` KDK steps on ``pos64``/``vel64`` in place.
+
+    Returns ``(acc, pot, traj)``: a(x) at the final positions ``[3, n]``, the final
+    potentials (or None) and the position checkpoints ``[nsteps + 1, 3, n]`` (or None).
+    With ``init=False`` ``acc`` must already hold a(pos64).
+    """
+    n = _check_pos(pos64, torch.float64, "pos64")
+    _check_pos(vel64, torch.float64, "vel64")
+    _check_vec(mass, n, torch.float32, "mass")
+    dev = pos64.device
+    if acc is None:
+        if not init:
+            raise ValueError("acc is required when init=False")
+        acc = torch.empty((3, n), dtype=torch.float64, device=dev)
+    pot = torch.empty(n, dtype=torch.float64, device=dev) if with_pot else None
+    traj = (torch.empty((nsteps + 1, 3, n), dtype=torch.float64, device=dev)
+            if keep_trajectory else None)
+    opts = make_opts(precision=precision, centre=centre, **kw)
+    _lib.nbody_leapfrog(n, pos64.data_ptr(), vel64.data_ptr(), mass.data_ptr(), float(eps),
+                        float(dt), int(nsteps), acc.data_ptr(),
+                        pot.data_ptr() if pot is not None else None,
+                        traj.data_ptr() if traj is not None else None,
+                        _lib.NBODY_LF_INIT_ACC if init else 0, opts, stream_ptr())
+    return acc, pot, traj
+
+
+class LeapfrogGraph:
+    """A HIP graph of ``nsteps`` KDK steps on fixed tensors (replayed by ``launch``).
+
+    The tensors are referenced, not copied: keep them alive and update them in place.
+    ``acc`` must hold a(pos64) before the first launch.
+    """
+
+    def __init__(self, pos64, vel64, mass, eps, dt, nsteps, acc, pot=None, precision="comp",
+                 centre="system", **kw):
+        n = _check_pos(pos64, torch.float64, "pos64")
+        _check_pos(vel64, torch.float64, "vel64")
+        _check_pos(acc, torch.float64, "acc")
+        _check_vec(mass, n, torch.float32, "mass")
+        self._keep = (pos64, vel64, mass, acc, pot)
+        opts = make_opts(precision=precision, centre=centre, **kw)
+        self.handle = _lib.nbody_graph_create_leapfrog(
+            n, pos64.data_ptr(), vel64.data_ptr(), mass.data_ptr(), float(eps), float(dt),
+            int(nsteps), acc.data_ptr(), pot.data_ptr() if pot is not None else None, opts,
+            stream_ptr())
+
+    def launch(self, stream: torch.cuda.Stream | None = None):
+        _lib.nbody_graph_launch(self.handle, stream_ptr(stream))
+
+    def close(self):
+        if self.handle:
+            _lib.nbody_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

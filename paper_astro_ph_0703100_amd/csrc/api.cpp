@@ -26,8 +26,9 @@ std::mutex g_dev_mu;
 bool g_dev_ready[kMaxDevices];
 DeviceInfo g_dev[kMaxDevices];
 
-size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 }  // namespace
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 nbody_status set_error(nbody_status code, const std::string &msg) {
     g_error = msg;
@@ -147,11 +148,12 @@ size_t partial_bytes(const TileCfg &c, int precision) {
     return align_up((size_t)c.nseg * partial_words(precision) * (size_t)c.npad * 4, 256);
 }
 
-}  // namespace nbody
-
-using namespace nbody;
-
-namespace {
+nbody_opts resolve_opts(const nbody_opts *opts) {
+    nbody_opts o;
+    nbody_opts_default(&o);
+    if (opts) o = *opts;
+    return o;
+}
 
 nbody_status check_common(int64_t n, const void *pos, const void *mass, float eps,
                           const void *acc, const nbody_opts &o) {
@@ -169,24 +171,55 @@ nbody_status check_common(int64_t n, const void *pos, const void *mass, float ep
     return NBODY_OK;
 }
 
-template <typename T>
-bool misaligned(const T *p) {
-    return reinterpret_cast<uintptr_t>(p) % alignof(T) != 0;
+size_t f64_scratch_bytes(int64_t n, const TileCfg &cfg, int precision) {
+    return partial_bytes(cfg, precision) + align_up(sizeof(float) * 3 * (size_t)n, 256) +
+           align_up(centre_scratch_bytes() + 4 * sizeof(double), 256);
 }
+
+F64Scratch f64_scratch_layout(void *ws, int64_t n, const TileCfg &cfg, int precision) {
+    char *base = static_cast<char *>(ws);
+    const size_t pb = partial_bytes(cfg, precision);
+    const size_t xb = align_up(sizeof(float) * 3 * (size_t)n, 256);
+    F64Scratch r;
+    r.part = base;
+    r.x32 = reinterpret_cast<float *>(base + pb);
+    r.centre = reinterpret_cast<double *>(base + pb + xb);
+    r.centre_scratch = r.centre + 4;
+    return r;
+}
+
+namespace {
 
 // Pair kernel + FP64 reduction on FP32 structure-of-arrays positions.
 nbody_status force_f32_core(int64_t n, const float *pos, const float *mass, float eps, double *acc,
                             double *pot, const nbody_opts &o, const TileCfg &cfg, void *ws,
-                            hipStream_t s) {
+                            double *kick_v, double kick_h, hipStream_t s) {
     const float e2 = eps * eps;
     PairArgs pa{pos, pos + n, pos + 2 * n, mass, (int)n, cfg.seg_len, e2, ws, cfg.npad};
     nbody_status st = launch_pair(cfg, o.precision, pot != nullptr, pa, s);
     if (st) return st;
-    FinalizeArgs fa{ws, cfg.nseg, cfg.npad, (int)n, mass, e2, o.self_pot, acc, pot};
+    FinalizeArgs fa{ws, cfg.nseg, cfg.npad, (int)n, mass, e2, o.self_pot, acc, pot, kick_v, kick_h};
     return launch_finalize(o.precision, fa, s);
 }
 
 }  // namespace
+
+nbody_status force_f64_core(int64_t n, const double *pos64, const float *mass, float eps,
+                            double *acc, double *pot, const nbody_opts &o, const TileCfg &cfg,
+                            const F64Scratch &ws, double *kick_v, double kick_h, hipStream_t s) {
+    nbody_status st;
+    if (o.centre == NBODY_CENTRE_SYSTEM) {
+        if ((st = launch_centre(n, pos64, ws.centre, ws.centre_scratch, s))) return st;
+        if ((st = launch_convert(n, pos64, ws.centre, ws.x32, s))) return st;
+    } else {
+        if ((st = launch_convert(n, pos64, nullptr, ws.x32, s))) return st;
+    }
+    return force_f32_core(n, ws.x32, mass, eps, acc, pot, o, cfg, ws.part, kick_v, kick_h, s);
+}
+
+}  // namespace nbody
+
+using namespace nbody;
 
 extern "C" {
 
@@ -209,10 +242,7 @@ size_t nbody_workspace_size(int64_t n, const nbody_opts *opts) {
     if (n <= 0) return 0;
     TileCfg c;
     if (choose_cfg(n, o.precision, o, &c) != NBODY_OK) return 0;
-    size_t b = partial_bytes(c, o.precision);
-    b += align_up(sizeof(float) * 3 * (size_t)n, 256);  // FP32 relative positions
-    b += align_up(centre_scratch_bytes() + 4 * sizeof(double), 256);
-    return b;
+    return f64_scratch_bytes(n, c, o.precision);
 }
 
 nbody_status nbody_force_ex(int64_t n, const float *pos, const float *mass, float eps, double *acc,
@@ -231,7 +261,7 @@ nbody_status nbody_force_ex(int64_t n, const float *pos, const float *mass, floa
     if ((st = choose_cfg(n, o.precision, o, &cfg))) return st;
     void *ws = nullptr;
     if ((st = get_workspace(o, partial_bytes(cfg, o.precision), s, &ws))) return st;
-    return force_f32_core(n, pos, mass, eps, acc, pot, o, cfg, ws, s);
+    return force_f32_core(n, pos, mass, eps, acc, pot, o, cfg, ws, nullptr, 0.0, s);
 }
 
 nbody_status nbody_force(int64_t n, const float *pos, const float *mass, float eps, double *acc,
@@ -242,9 +272,7 @@ nbody_status nbody_force(int64_t n, const float *pos, const float *mass, float e
 nbody_status nbody_force_f64(int64_t n, const double *pos64, const float *mass, float eps,
                              double *acc, double *pot, const nbody_opts *opts, void *stream) {
     clear_error();
-    nbody_opts o;
-    nbody_opts_default(&o);
-    if (opts) o = *opts;
+    nbody_opts o = resolve_opts(opts);
     nbody_status st = check_common(n, pos64, mass, eps, acc, o);
     if (st) return st;
     if (misaligned(pos64) || misaligned(mass) || misaligned(acc) || misaligned(pot))
@@ -255,22 +283,10 @@ nbody_status nbody_force_f64(int64_t n, const double *pos64, const float *mass, 
     hipStream_t s = static_cast<hipStream_t>(stream);
     TileCfg cfg;
     if ((st = choose_cfg(n, o.precision, o, &cfg))) return st;
-    const size_t pb = partial_bytes(cfg, o.precision);
-    const size_t xb = align_up(sizeof(float) * 3 * (size_t)n, 256);
-    const size_t cb = align_up(centre_scratch_bytes() + 4 * sizeof(double), 256);
     void *ws = nullptr;
-    if ((st = get_workspace(o, pb + xb + cb, s, &ws))) return st;
-    char *base = static_cast<char *>(ws);
-    float *x32 = reinterpret_cast<float *>(base + pb);
-    double *cen = reinterpret_cast<double *>(base + pb + xb);
-    double *cscr = cen + 4;
-    if (o.centre == NBODY_CENTRE_SYSTEM) {
-        if ((st = launch_centre(n, pos64, cen, cscr, s))) return st;
-        if ((st = launch_convert(n, pos64, cen, x32, s))) return st;
-    } else {
-        if ((st = launch_convert(n, pos64, nullptr, x32, s))) return st;
-    }
-    return force_f32_core(n, x32, mass, eps, acc, pot, o, cfg, ws, s);
+    if ((st = get_workspace(o, f64_scratch_bytes(n, cfg, o.precision), s, &ws))) return st;
+    return force_f64_core(n, pos64, mass, eps, acc, pot, o, cfg,
+                          f64_scratch_layout(ws, n, cfg, o.precision), nullptr, 0.0, s);
 }
 
 }  // extern "C"

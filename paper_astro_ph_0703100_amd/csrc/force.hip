@@ -200,7 +200,8 @@ __global__ __launch_bounds__(kTPB) void pair_kernel(PairArgs a) {
 
 // Sum of the segment partials of one particle in a fixed order, then removal of the
 // j == i potential term -m_i * rsq(eps^2), recomputed with the same FP32 operations
-// the pair kernel used for it.  PLAIN adds in FP32; the other modes in FP64.
+// the pair kernel used for it.  PLAIN adds in FP32; the other modes in FP64.  With
+// kick_v set, the velocity kick of a leapfrog step follows in FP64.
 template <int MODE>
 __global__ __launch_bounds__(256) void finalize_kernel(FinalizeArgs a) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -241,6 +242,10 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinalizeArgs a) {
     a.acc[(size_t)a.n + i] = r[1];
     a.acc[2 * (size_t)a.n + i] = r[2];
     if (a.pot) a.pot[i] = r[3];
+    if (a.kick_v) {  // second kick of a leapfrog step, fused: v += h a
+#pragma unroll
+        for (int c = 0; c < 3; ++c) a.kick_v[c * (size_t)a.n + i] += a.kick_h * r[c];
+    }
 }
 
 // Two-stage fixed-order FP64 mean of the positions [3][n]: kCentreBlocks partial

@@ -1,0 +1,60 @@
+// FP64 element-wise kernels of the kick-drift-kick leapfrog.  The state is
+// structure-of-arrays [3][n] doubles; one lane per element of the 3n-vector.
+#include "nbody_internal.h"
+
+namespace nbody {
+namespace {
+
+// First half-kick fused with the drift: v += h a; x += dt v.
+__global__ __launch_bounds__(256) void kick_drift_kernel(int64_t count, double *__restrict__ x,
+                                                        double *__restrict__ v,
+                                                        const double *__restrict__ a, double h,
+                                                        double dt) {
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= count) return;
+    const double vv = v[q] + h * a[q];
+    v[q] = vv;
+    x[q] = x[q] + dt * vv;
+}
+
+__global__ __launch_bounds__(256) void kick_kernel(int64_t count, double *__restrict__ v,
+                                                  const double *__restrict__ a, double h) {
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= count) return;
+    v[q] = v[q] + h * a[q];
+}
+
+__global__ __launch_bounds__(256) void copy_f64_kernel(int64_t count, const double *__restrict__ src,
+                                                      double *__restrict__ dst) {
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= count) return;
+    dst[q] = src[q];
+}
+
+dim3 grid_for(int64_t count) { return dim3((unsigned)((count + 255) / 256)); }
+
+}  // namespace
+
+nbody_status launch_kick_drift(int64_t n, double *x, double *v, const double *acc, double h,
+                               double dt, hipStream_t s) {
+    if (n <= 0) return NBODY_OK;
+    hipLaunchKernelGGL(kick_drift_kernel, grid_for(3 * n), dim3(256), 0, s, 3 * n, x, v, acc, h, dt);
+    NBODY_HIP_CHECK(hipGetLastError());
+    return NBODY_OK;
+}
+
+nbody_status launch_kick(int64_t n, double *v, const double *acc, double h, hipStream_t s) {
+    if (n <= 0) return NBODY_OK;
+    hipLaunchKernelGGL(kick_kernel, grid_for(3 * n), dim3(256), 0, s, 3 * n, v, acc, h);
+    NBODY_HIP_CHECK(hipGetLastError());
+    return NBODY_OK;
+}
+
+nbody_status launch_copy_f64(int64_t count, const double *src, double *dst, hipStream_t s) {
+    if (count <= 0) return NBODY_OK;
+    hipLaunchKernelGGL(copy_f64_kernel, grid_for(count), dim3(256), 0, s, count, src, dst);
+    NBODY_HIP_CHECK(hipGetLastError());
+    return NBODY_OK;
+}
+
+}  // namespace nbody

@@ -53,6 +53,8 @@ struct FinalizeArgs {
     int self_pot;      // 1: keep the j == i term of phi
     double *acc;       // [3][n]
     double *pot;       // [n] or nullptr
+    double *kick_v;    // [3][n]: if not null, v += kick_h * a after a is written
+    double kick_h;
 };
 
 // Thread-local error reporting.
@@ -65,6 +67,39 @@ void clear_error();
         hipError_t _e = (expr);                                 \
         if (_e != hipSuccess) return ::nbody::hip_error(_e, #expr); \
     } while (0)
+
+// True if p is not aligned for T (NULL counts as aligned).
+template <typename T>
+inline bool misaligned(const T *p) {
+    return reinterpret_cast<uintptr_t>(p) % alignof(T) != 0;
+}
+
+// Host helpers (api.cpp).
+bool stream_capturing(hipStream_t s);
+nbody_status get_workspace(const nbody_opts &o, size_t need, hipStream_t s, void **out);
+nbody_status choose_cfg(int64_t n, int precision, const nbody_opts &o, TileCfg *cfg);
+size_t partial_bytes(const TileCfg &c, int precision);
+size_t align_up(size_t v, size_t a);
+nbody_status check_common(int64_t n, const void *pos, const void *mass, float eps,
+                          const void *acc, const nbody_opts &o);
+nbody_opts resolve_opts(const nbody_opts *opts);
+
+// Scratch layout of one FP64-position force evaluation: partial sums, FP32 relative
+// positions [3][n], reference centre (4 doubles) and the centre-reduction partials.
+struct F64Scratch {
+    void *part;
+    float *x32;
+    double *centre;
+    double *centre_scratch;
+};
+size_t f64_scratch_bytes(int64_t n, const TileCfg &cfg, int precision);
+F64Scratch f64_scratch_layout(void *ws, int64_t n, const TileCfg &cfg, int precision);
+
+// One force evaluation from FP64 positions: centre + conversion (per opts.centre),
+// pair kernel, FP64 finalize (optionally followed by v += kick_h * a).
+nbody_status force_f64_core(int64_t n, const double *pos64, const float *mass, float eps,
+                            double *acc, double *pot, const nbody_opts &o, const TileCfg &cfg,
+                            const F64Scratch &ws, double *kick_v, double kick_h, hipStream_t s);
 
 // Device properties cached per device.
 struct DeviceInfo {
@@ -83,5 +118,10 @@ nbody_status launch_convert(int64_t n, const double *pos64, const double *centre
                             hipStream_t s);
 // Bytes of the centre-reduction scratch (partials of the two-stage FP64 sum).
 size_t centre_scratch_bytes();
+// Leapfrog pieces (leapfrog.hip).
+nbody_status launch_kick_drift(int64_t n, double *x, double *v, const double *acc, double h,
+                               double dt, hipStream_t s);
+nbody_status launch_kick(int64_t n, double *v, const double *acc, double h, hipStream_t s);
+nbody_status launch_copy_f64(int64_t count, const double *src, double *dst, hipStream_t s);
 
 }  // namespace nbody

@@ -111,3 +111,39 @@ def test_workspace_size_grows_with_n_and_mode():
 def test_zero_particles_is_a_noop_without_device_access():
     # n = 0 returns before any HIP call, even with NULL arrays.
     assert _lib.nbody_force(0, None, None, 0.1, None, None, None, check=False) == _lib.NBODY_OK
+
+
+def test_leapfrog_rejects_invalid_arguments():
+    o = _lib.nbody_opts_default()
+    ok = (100, FAKE, FAKE, FAKE, 0.1, 0.01, 2, FAKE, None, None, 0, o, None)
+
+    def call(**kw):
+        names = ["n", "x", "v", "m", "eps", "dt", "nsteps", "acc", "pot", "traj", "flags", "opts",
+                 "stream"]
+        args = dict(zip(names, ok))
+        args.update(kw)
+        return _lib.nbody_leapfrog(*[args[k] for k in names], check=False)
+
+    assert call(nsteps=-1) == _lib.NBODY_EINVAL
+    assert call(dt=float("inf")) == _lib.NBODY_EINVAL
+    assert call(dt=float("nan")) == _lib.NBODY_EINVAL
+    assert call(v=None) == _lib.NBODY_EINVAL
+    assert call(flags=4) == _lib.NBODY_EINVAL
+    assert call(eps=0.0) == _lib.NBODY_EINVAL
+    assert call(x=FAKE + 4) == _lib.NBODY_EINVAL
+    assert call(n=0, x=None, v=None, m=None, acc=None) == _lib.NBODY_OK
+
+
+def test_graph_create_rejects_invalid_arguments():
+    import ctypes
+    o = _lib.nbody_opts_default()
+    h = ctypes.c_void_p()
+    lib = _lib.load()
+    st = lib.nbody_graph_create_leapfrog(0, None, None, None, 0.1, 0.01, 1, None, None,
+                                         ctypes.byref(o), None, ctypes.byref(h))
+    assert st == _lib.NBODY_EINVAL and not h.value
+    st = lib.nbody_graph_create_leapfrog(100, FAKE, FAKE, FAKE, 0.1, 0.01, -3, FAKE, None,
+                                         ctypes.byref(o), None, ctypes.byref(h))
+    assert st == _lib.NBODY_EINVAL
+    assert lib.nbody_graph_launch(None, None) == _lib.NBODY_EINVAL
+    lib.nbody_graph_destroy(None)
