@@ -151,6 +151,38 @@ NBODY_API nbody_status nbody_graph_create_leapfrog(int64_t n, double *pos64, dou
 NBODY_API nbody_status nbody_graph_launch(nbody_graph *graph, void *stream);
 NBODY_API void nbody_graph_destroy(nbody_graph *graph);
 
+/* ------------------------------------------------------------------------------
+ * Adjoint (vector-Jacobian product) of one force evaluation.  Given cotangents
+ * g = dL/da and p = dL/dphi it returns, with d = x_j - x_k, s^2 = |d|^2 + eps^2,
+ * w = m_k g_j - m_j g_k and q = m_k p_j + m_j p_k (sums over j != k):
+ *     grad_pos_k  = sum_j [ w / s^3 - 3 (d . w) d / s^5 - q d / s^3 ]
+ *     grad_mass_k = -sum_j [ (g_j . d) / s^3 + p_j / s ]
+ * the derivative of eq. (1) and of the potential with respect to positions and masses.
+ *   g_acc      double [3][n] (read)          g_pot   double [n] or NULL (= 0)
+ *   grad_pos   double [3][n] (written)       grad_mass double [n] or NULL (skipped)
+ * Pair arithmetic FP32 (positions as in nbody_force / nbody_force_f64), accumulation
+ * per opts->precision, FP64 reduction.
+ * ---------------------------------------------------------------------------- */
+NBODY_API nbody_status nbody_force_vjp(int64_t n, const float *pos, const float *mass, float eps,
+                                       const double *g_acc, const double *g_pot, double *grad_pos,
+                                       double *grad_mass, const nbody_opts *opts, void *stream);
+NBODY_API nbody_status nbody_force_vjp_f64(int64_t n, const double *pos64, const float *mass,
+                                           float eps, const double *g_acc, const double *g_pot,
+                                           double *grad_pos, double *grad_mass,
+                                           const nbody_opts *opts, void *stream);
+
+/* Reverse pass of nsteps KDK steps (nbody_leapfrog) from the checkpoints it stored.
+ *   traj   double [nsteps+1][3][n]: x_0 .. x_nsteps (read)
+ *   xbar   double [3][n]: on entry dL/dx_nsteps, on exit dL/dx_0
+ *   vbar   double [3][n]: on entry dL/dv_nsteps, on exit dL/dv_0
+ *   mbar   double [n] or NULL: dL/dm (through the dynamics) is ADDED to it
+ * The cotangents of a(x_t) from the two kicks that use it are summed before one VJP
+ * (nbody_force_vjp_f64 with the same options) per checkpoint. */
+NBODY_API nbody_status nbody_leapfrog_adjoint(int64_t n, const double *traj, const float *mass,
+                                              float eps, double dt, int32_t nsteps, double *xbar,
+                                              double *vbar, double *mbar, const nbody_opts *opts,
+                                              void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -77,6 +77,9 @@ SIGNATURES = {
                                            ctypes.POINTER(_P)]),
     "nbody_graph_launch": (_I32, [_P, _P]),
     "nbody_graph_destroy": (None, [_P]),
+    "nbody_force_vjp": (_I32, [_I64, _P, _P, _F, _P, _P, _P, _P, _OPTS, _P]),
+    "nbody_force_vjp_f64": (_I32, [_I64, _P, _P, _F, _P, _P, _P, _P, _OPTS, _P]),
+    "nbody_leapfrog_adjoint": (_I32, [_I64, _P, _P, _F, _D, _I32, _P, _P, _P, _OPTS, _P]),
 }
 
 NBODY_LF_INIT_ACC = 1
@@ -168,3 +171,24 @@ def nbody_graph_launch(graph, stream, check=True):
 
 def nbody_graph_destroy(graph):
     load().nbody_graph_destroy(graph)
+
+
+def nbody_force_vjp(n, pos, mass, eps, g_acc, g_pot, grad_pos, grad_mass, opts, stream,
+                    check=True):
+    st = load().nbody_force_vjp(n, pos, mass, eps, g_acc, g_pot, grad_pos, grad_mass,
+                                _opt_ref(opts), stream)
+    return _check(st, "nbody_force_vjp") if check else st
+
+
+def nbody_force_vjp_f64(n, pos64, mass, eps, g_acc, g_pot, grad_pos, grad_mass, opts, stream,
+                        check=True):
+    st = load().nbody_force_vjp_f64(n, pos64, mass, eps, g_acc, g_pot, grad_pos, grad_mass,
+                                    _opt_ref(opts), stream)
+    return _check(st, "nbody_force_vjp_f64") if check else st
+
+
+def nbody_leapfrog_adjoint(n, traj, mass, eps, dt, nsteps, xbar, vbar, mbar, opts, stream,
+                           check=True):
+    st = load().nbody_leapfrog_adjoint(n, traj, mass, eps, dt, nsteps, xbar, vbar, mbar,
+                                       _opt_ref(opts), stream)
+    return _check(st, "nbody_leapfrog_adjoint") if check else st

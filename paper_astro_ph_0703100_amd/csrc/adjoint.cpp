@@ -1,0 +1,142 @@
+// Host side of the adjoint: the VJP of one force evaluation and the reverse pass of
+// the kick-drift-kick leapfrog over stored position checkpoints.
+#include <cmath>
+
+#include "nbody_internal.h"
+#include "tuning.h"
+
+namespace nbody {
+namespace {
+
+nbody_status check_vjp(int64_t n, const void *pos, const float *mass, float eps,
+                       const double *g_acc, const double *g_pot, const double *grad_pos,
+                       const double *grad_mass, const nbody_opts &o) {
+    nbody_status st = check_common(n, pos, mass, eps, grad_pos, o);
+    if (st) return st;
+    if (n > 0 && !g_acc) return set_error(NBODY_EINVAL, "g_acc must not be NULL");
+    if (misaligned(mass) || misaligned(g_acc) || misaligned(g_pot) || misaligned(grad_pos) ||
+        misaligned(grad_mass))
+        return set_error(NBODY_EINVAL, "misaligned array argument");
+    if (o.centre == NBODY_CENTRE_TILE)
+        return set_error(NBODY_EUNSUPPORTED, "NBODY_CENTRE_TILE is not available");
+    return NBODY_OK;
+}
+
+size_t vjp_f64_bytes(int64_t n, const TileCfg &cfg, int precision) {
+    return f64_scratch_bytes(n, cfg, precision);
+}
+
+// Adjoint pair kernel + FP64 finalize on FP32 positions.
+nbody_status vjp_f32_core(int64_t n, const float *pos, const float *mass, float eps,
+                          const double *g_acc, const double *g_pot, double *grad_pos,
+                          double *grad_mass, bool accumulate, const nbody_opts &o,
+                          const TileCfg &cfg, void *part, hipStream_t s) {
+    const float e2 = eps * eps;
+    VjpArgs va{pos,   pos + n, pos + 2 * n, mass, g_acc, g_acc + n, g_acc + 2 * n,
+               g_pot, (int)n,  cfg.seg_len, e2,   part,  cfg.npad};
+    nbody_status st = launch_vjp(cfg, o.precision, va, grad_mass != nullptr, s);
+    if (st) return st;
+    VjpFinalizeArgs fa{part,     cfg.nseg,  cfg.npad, (int)n, g_pot, e2, grad_pos, grad_mass,
+                       accumulate ? 1 : 0};
+    return launch_vjp_finalize(o.precision, fa, s);
+}
+
+// Centre + FP32 conversion, then the adjoint on the converted positions.
+nbody_status vjp_f64_core(int64_t n, const double *pos64, const float *mass, float eps,
+                          const double *g_acc, const double *g_pot, double *grad_pos,
+                          double *grad_mass, bool accumulate, const nbody_opts &o,
+                          const TileCfg &cfg, const F64Scratch &ws, hipStream_t s) {
+    nbody_status st;
+    if (o.centre == NBODY_CENTRE_SYSTEM) {
+        if ((st = launch_centre(n, pos64, ws.centre, ws.centre_scratch, s))) return st;
+        if ((st = launch_convert(n, pos64, ws.centre, ws.x32, s))) return st;
+    } else {
+        if ((st = launch_convert(n, pos64, nullptr, ws.x32, s))) return st;
+    }
+    return vjp_f32_core(n, ws.x32, mass, eps, g_acc, g_pot, grad_pos, grad_mass, accumulate, o,
+                        cfg, ws.part, s);
+}
+
+}  // namespace
+}  // namespace nbody
+
+using namespace nbody;
+
+extern "C" {
+
+nbody_status nbody_force_vjp(int64_t n, const float *pos, const float *mass, float eps,
+                             const double *g_acc, const double *g_pot, double *grad_pos,
+                             double *grad_mass, const nbody_opts *opts, void *stream) {
+    clear_error();
+    nbody_opts o = resolve_opts(opts);
+    nbody_status st = check_vjp(n, pos, mass, eps, g_acc, g_pot, grad_pos, grad_mass, o);
+    if (st) return st;
+    if (misaligned(pos)) return set_error(NBODY_EINVAL, "misaligned array argument");
+    if (n == 0) return NBODY_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    TileCfg cfg;
+    if ((st = choose_cfg(KERNEL_VJP, n, o.precision, o, &cfg))) return st;
+    void *ws = nullptr;
+    if ((st = get_workspace(o, partial_bytes(cfg, o.precision), s, &ws))) return st;
+    return vjp_f32_core(n, pos, mass, eps, g_acc, g_pot, grad_pos, grad_mass, false, o, cfg, ws, s);
+}
+
+nbody_status nbody_force_vjp_f64(int64_t n, const double *pos64, const float *mass, float eps,
+                                 const double *g_acc, const double *g_pot, double *grad_pos,
+                                 double *grad_mass, const nbody_opts *opts, void *stream) {
+    clear_error();
+    nbody_opts o = resolve_opts(opts);
+    nbody_status st = check_vjp(n, pos64, mass, eps, g_acc, g_pot, grad_pos, grad_mass, o);
+    if (st) return st;
+    if (misaligned(pos64)) return set_error(NBODY_EINVAL, "misaligned array argument");
+    if (n == 0) return NBODY_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    TileCfg cfg;
+    if ((st = choose_cfg(KERNEL_VJP, n, o.precision, o, &cfg))) return st;
+    void *ws = nullptr;
+    if ((st = get_workspace(o, vjp_f64_bytes(n, cfg, o.precision), s, &ws))) return st;
+    return vjp_f64_core(n, pos64, mass, eps, g_acc, g_pot, grad_pos, grad_mass, false, o, cfg,
+                        f64_scratch_layout(ws, n, cfg, o.precision), s);
+}
+
+nbody_status nbody_leapfrog_adjoint(int64_t n, const double *traj, const float *mass, float eps,
+                                    double dt, int32_t nsteps, double *xbar, double *vbar,
+                                    double *mbar, const nbody_opts *opts, void *stream) {
+    clear_error();
+    nbody_opts o = resolve_opts(opts);
+    nbody_status st = check_common(n, traj, mass, eps, xbar, o);
+    if (st) return st;
+    if (n > 0 && !vbar) return set_error(NBODY_EINVAL, "vbar must not be NULL");
+    if (nsteps < 0) return set_error(NBODY_EINVAL, "nsteps must be >= 0");
+    if (!std::isfinite(dt)) return set_error(NBODY_EINVAL, "dt must be finite");
+    if (misaligned(traj) || misaligned(mass) || misaligned(xbar) || misaligned(vbar) ||
+        misaligned(mbar))
+        return set_error(NBODY_EINVAL, "misaligned array argument");
+    if (o.centre == NBODY_CENTRE_TILE)
+        return set_error(NBODY_EUNSUPPORTED, "NBODY_CENTRE_TILE is not available");
+    if (n == 0) return NBODY_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    TileCfg cfg;
+    if ((st = choose_cfg(KERNEL_VJP, n, o.precision, o, &cfg))) return st;
+    const size_t base = vjp_f64_bytes(n, cfg, o.precision);
+    const size_t n3 = 3 * (size_t)n;
+    void *ws = nullptr;
+    if ((st = get_workspace(o, base + sizeof(double) * n3, s, &ws))) return st;
+    const F64Scratch lay = f64_scratch_layout(ws, n, cfg, o.precision);
+    double *abar = reinterpret_cast<double *>(static_cast<char *>(ws) + base);
+    const double h = 0.5 * dt;
+
+    // abar holds the cotangent of a(x_t) summed over the two kicks that use it.
+    if ((st = launch_fill_f64((int64_t)n3, abar, 0.0, s))) return st;
+    for (int32_t t = nsteps - 1; t >= 0; --t) {
+        const double *x1 = traj + (size_t)(t + 1) * n3;
+        if ((st = launch_axpy_f64((int64_t)n3, abar, h, vbar, s))) return st;  // second kick
+        if ((st = vjp_f64_core(n, x1, mass, eps, abar, nullptr, xbar, mbar, true, o, cfg, lay, s)))
+            return st;
+        // drift (vbar += dt xbar) and first kick of step t (abar = h vbar)
+        if ((st = launch_adj_drift_kick((int64_t)n3, vbar, xbar, abar, dt, h, s))) return st;
+    }
+    return vjp_f64_core(n, traj, mass, eps, abar, nullptr, xbar, mbar, true, o, cfg, lay, s);
+}
+
+}  // extern "C"

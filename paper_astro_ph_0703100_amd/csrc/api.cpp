@@ -111,9 +111,9 @@ nbody_status get_workspace(const nbody_opts &o, size_t need, hipStream_t s, void
 
 // Launch shape for n particles: explicit options first, then the tuning table, then
 // a default that gives every compute unit several blocks.
-nbody_status choose_cfg(int64_t n, int precision, const nbody_opts &o, TileCfg *cfg) {
+nbody_status choose_cfg(int kernel, int64_t n, int precision, const nbody_opts &o, TileCfg *cfg) {
     TileCfg c;
-    TuneEntry t = tuned_shape(KERNEL_FORCE, precision, n);
+    TuneEntry t = tuned_shape(kernel, precision, n);
     c.ipl = o.ipl ? o.ipl : t.ipl;
     c.jt = o.jtile ? o.jtile : t.jt;
     if (!(c.ipl == 1 || c.ipl == 2 || c.ipl == 4 || c.ipl == 8))
@@ -198,7 +198,8 @@ nbody_status force_f32_core(int64_t n, const float *pos, const float *mass, floa
     PairArgs pa{pos, pos + n, pos + 2 * n, mass, (int)n, cfg.seg_len, e2, ws, cfg.npad};
     nbody_status st = launch_pair(cfg, o.precision, pot != nullptr, pa, s);
     if (st) return st;
-    FinalizeArgs fa{ws, cfg.nseg, cfg.npad, (int)n, mass, e2, o.self_pot, acc, pot, kick_v, kick_h};
+    FinalizeArgs fa{ws,   cfg.nseg, cfg.npad, (int)n, mass, e2, o.self_pot ? 0 : 1,
+                    acc, pot,      kick_v,   kick_h};
     return launch_finalize(o.precision, fa, s);
 }
 
@@ -241,7 +242,7 @@ size_t nbody_workspace_size(int64_t n, const nbody_opts *opts) {
     if (opts) o = *opts;
     if (n <= 0) return 0;
     TileCfg c;
-    if (choose_cfg(n, o.precision, o, &c) != NBODY_OK) return 0;
+    if (choose_cfg(KERNEL_FORCE, n, o.precision, o, &c) != NBODY_OK) return 0;
     return f64_scratch_bytes(n, c, o.precision);
 }
 
@@ -258,7 +259,7 @@ nbody_status nbody_force_ex(int64_t n, const float *pos, const float *mass, floa
     if (n == 0) return NBODY_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
     TileCfg cfg;
-    if ((st = choose_cfg(n, o.precision, o, &cfg))) return st;
+    if ((st = choose_cfg(KERNEL_FORCE, n, o.precision, o, &cfg))) return st;
     void *ws = nullptr;
     if ((st = get_workspace(o, partial_bytes(cfg, o.precision), s, &ws))) return st;
     return force_f32_core(n, pos, mass, eps, acc, pot, o, cfg, ws, nullptr, 0.0, s);
@@ -282,7 +283,7 @@ nbody_status nbody_force_f64(int64_t n, const double *pos64, const float *mass, 
     if (n == 0) return NBODY_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
     TileCfg cfg;
-    if ((st = choose_cfg(n, o.precision, o, &cfg))) return st;
+    if ((st = choose_cfg(KERNEL_FORCE, n, o.precision, o, &cfg))) return st;
     void *ws = nullptr;
     if ((st = get_workspace(o, f64_scratch_bytes(n, cfg, o.precision), s, &ws))) return st;
     return force_f64_core(n, pos64, mass, eps, acc, pot, o, cfg,

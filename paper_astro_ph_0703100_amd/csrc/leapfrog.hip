@@ -31,6 +31,31 @@ __global__ __launch_bounds__(256) void copy_f64_kernel(int64_t count, const doub
     dst[q] = src[q];
 }
 
+__global__ __launch_bounds__(256) void fill_f64_kernel(int64_t count, double *__restrict__ dst,
+                                                      double value) {
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= count) return;
+    dst[q] = value;
+}
+
+__global__ __launch_bounds__(256) void axpy_f64_kernel(int64_t count, double *__restrict__ y,
+                                                      double alpha, const double *__restrict__ x) {
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= count) return;
+    y[q] = y[q] + alpha * x[q];
+}
+
+__global__ __launch_bounds__(256) void adj_drift_kick_kernel(int64_t count, double *__restrict__ vbar,
+                                                            const double *__restrict__ xbar,
+                                                            double *__restrict__ abar, double dt,
+                                                            double h) {
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= count) return;
+    const double vb = vbar[q] + dt * xbar[q];
+    vbar[q] = vb;
+    abar[q] = h * vb;
+}
+
 dim3 grid_for(int64_t count) { return dim3((unsigned)((count + 255) / 256)); }
 
 }  // namespace
@@ -53,6 +78,29 @@ nbody_status launch_kick(int64_t n, double *v, const double *acc, double h, hipS
 nbody_status launch_copy_f64(int64_t count, const double *src, double *dst, hipStream_t s) {
     if (count <= 0) return NBODY_OK;
     hipLaunchKernelGGL(copy_f64_kernel, grid_for(count), dim3(256), 0, s, count, src, dst);
+    NBODY_HIP_CHECK(hipGetLastError());
+    return NBODY_OK;
+}
+
+nbody_status launch_fill_f64(int64_t count, double *dst, double value, hipStream_t s) {
+    if (count <= 0) return NBODY_OK;
+    hipLaunchKernelGGL(fill_f64_kernel, grid_for(count), dim3(256), 0, s, count, dst, value);
+    NBODY_HIP_CHECK(hipGetLastError());
+    return NBODY_OK;
+}
+
+nbody_status launch_axpy_f64(int64_t count, double *y, double alpha, const double *x, hipStream_t s) {
+    if (count <= 0) return NBODY_OK;
+    hipLaunchKernelGGL(axpy_f64_kernel, grid_for(count), dim3(256), 0, s, count, y, alpha, x);
+    NBODY_HIP_CHECK(hipGetLastError());
+    return NBODY_OK;
+}
+
+nbody_status launch_adj_drift_kick(int64_t count, double *vbar, const double *xbar, double *abar,
+                                   double dt, double h, hipStream_t s) {
+    if (count <= 0) return NBODY_OK;
+    hipLaunchKernelGGL(adj_drift_kick_kernel, grid_for(count), dim3(256), 0, s, count, vbar, xbar,
+                       abar, dt, h);
     NBODY_HIP_CHECK(hipGetLastError());
     return NBODY_OK;
 }

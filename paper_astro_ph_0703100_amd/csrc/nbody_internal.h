@@ -50,11 +50,32 @@ struct FinalizeArgs {
     int nseg, npad, n;
     const float *m;
     float eps2;
-    int self_pot;      // 1: keep the j == i term of phi
+    int exclude_self;  // 1: remove the j == i potential term
     double *acc;       // [3][n]
     double *pot;       // [n] or nullptr
     double *kick_v;    // [3][n]: if not null, v += kick_h * a after a is written
     double kick_h;
+};
+
+struct VjpArgs {
+    const float *x, *y, *z, *m;      // FP32 positions [3][n] (relative to the centre) and masses
+    const double *gx, *gy, *gz;      // dL/da [3][n]
+    const double *gp;                // dL/dphi [n] or nullptr
+    int n;
+    int seg_len;
+    float eps2;
+    void *part;
+    int npad;
+};
+
+struct VjpFinalizeArgs {
+    const void *part;
+    int nseg, npad, n;
+    const double *gp;   // dL/dphi or nullptr
+    float eps2;
+    double *grad_pos;   // [3][n]
+    double *grad_mass;  // [n] or nullptr
+    int accumulate;     // 1: add into grad_pos / grad_mass instead of overwriting
 };
 
 // Thread-local error reporting.
@@ -77,7 +98,7 @@ inline bool misaligned(const T *p) {
 // Host helpers (api.cpp).
 bool stream_capturing(hipStream_t s);
 nbody_status get_workspace(const nbody_opts &o, size_t need, hipStream_t s, void **out);
-nbody_status choose_cfg(int64_t n, int precision, const nbody_opts &o, TileCfg *cfg);
+nbody_status choose_cfg(int kernel, int64_t n, int precision, const nbody_opts &o, TileCfg *cfg);
 size_t partial_bytes(const TileCfg &c, int precision);
 size_t align_up(size_t v, size_t a);
 nbody_status check_common(int64_t n, const void *pos, const void *mass, float eps,
@@ -123,5 +144,15 @@ nbody_status launch_kick_drift(int64_t n, double *x, double *v, const double *ac
                                double dt, hipStream_t s);
 nbody_status launch_kick(int64_t n, double *v, const double *acc, double h, hipStream_t s);
 nbody_status launch_copy_f64(int64_t count, const double *src, double *dst, hipStream_t s);
+nbody_status launch_fill_f64(int64_t count, double *dst, double value, hipStream_t s);
+// y += alpha * x
+nbody_status launch_axpy_f64(int64_t count, double *y, double alpha, const double *x, hipStream_t s);
+// Reverse of one leapfrog step's drift and first kick: vbar += dt * xbar; abar = h * vbar.
+nbody_status launch_adj_drift_kick(int64_t count, double *vbar, const double *xbar, double *abar,
+                                   double dt, double h, hipStream_t s);
+// Adjoint pair kernel and its FP64 finalize (vjp.hip).
+nbody_status launch_vjp(const TileCfg &cfg, int precision, const VjpArgs &a, bool with_mass,
+                        hipStream_t s);
+nbody_status launch_vjp_finalize(int precision, const VjpFinalizeArgs &a, hipStream_t s);
 
 }  // namespace nbody

@@ -1,0 +1,285 @@
+// Generic i-tile x j-tile pair engine for gfx950 (device code, header-only).
+//
+// The paper's library evaluates arbitrary pair interactions from a user "pipeline
+// description" that reads an i-record and a j-record and accumulates outputs
+// (Sec. 4.5, Appendix A).  This engine is that idea on CDNA4: a pipeline type `Op`
+// supplies the records and the pair body; the engine supplies the blocking.
+//
+//   * a block of 256 lanes owns an i-tile of 256 * IPL particles; each lane keeps IPL
+//     i-records in VGPRs (lane-strided so global loads and stores coalesce);
+//   * blockIdx.y selects a j-segment; the block walks it in LDS tiles of JT
+//     j-records, staged with coalesced loads and double-buffered (one barrier per
+//     tile), the J-BAG / J-PACKING of Sec. 2.2;
+//   * every lane reads each j-record from LDS with broadcast 16-byte reads and runs
+//     the pair body for its IPL i-records;
+//   * the j == i pair is evaluated like any other: every term that carries the
+//     separation is exactly zero there, and the pipelines round the remaining
+//     (potential-type) self term on its own so their finalize can remove it exactly;
+//   * accumulation (Sec. 2.2.2, eq. (2); Sec. 3.4):
+//       PLAIN   - one FP32 accumulator per output and (i, segment);
+//       FP64RED - FP32 partial over each block of kBlockJ j's, added into FP64;
+//       COMP    - FP32 partial over each block, added into an FP32 (hi, lo) pair by an
+//                 error-free two-sum;
+//   * partial sums go to scratch planes [segment][word][npad]; a finalize kernel adds
+//     the segments in a fixed order in FP64 (PLAIN: FP32).
+// No atomics: every result is a fixed-order sum, bitwise reproducible per launch shape.
+//
+// An Op provides:
+//   static constexpr int kJWords;            // floats per j-record (multiple of 4)
+//   static constexpr int kOut;               // outputs per i (<= 4)
+//   struct Args;                             // kernel arguments (n, seg_len, eps2, part, npad, ...)
+//   struct IState;                           // per-i registers
+//   static IState load_i(const Args&, int i);
+//   static void load_j(const Args&, int j, float (&r)[kJWords]);
+//   static void pad_j(float (&r)[kJWords]);  // a record that adds exactly zero
+//   template <bool FULL> static void pair(const float *jr, const IState&, float eps2,
+//                                         float (&acc)[kOut]);
+//   (FULL = false may skip the last output.)
+#pragma once
+
+#include "nbody_internal.h"
+
+namespace nbody {
+namespace engine {
+
+// Knuth's error-free sum: hi + lo += b with hi = fl(hi + b) and the rounding error of
+// that addition added to lo.
+__device__ __forceinline__ void two_sum(float &hi, float &lo, float b) {
+    const float s = hi + b;
+    const float bb = s - hi;
+    const float err = (hi - (s - bb)) + (b - bb);
+    hi = s;
+    lo = lo + err;
+}
+
+// One LDS tile: all JT j-records against the lane's IPL i-records.
+template <class Op, int IPL, int JT, int MODE, bool FULL>
+__device__ __forceinline__ void tile_pass(const float4 *tl, const typename Op::IState (&is)[IPL],
+                                          float eps2, float (&hs)[IPL][Op::kOut],
+                                          float (&ls)[IPL][Op::kOut],
+                                          double (&ds)[IPL][Op::kOut]) {
+    constexpr int W = Op::kJWords;
+    constexpr int NO = Op::kOut;
+    auto read = [&](int jj, float (&jr)[W]) {
+#pragma unroll
+        for (int v = 0; v < W / 4; ++v) {
+            const float4 q4 = tl[jj * (W / 4) + v];
+            jr[4 * v] = q4.x;
+            jr[4 * v + 1] = q4.y;
+            jr[4 * v + 2] = q4.z;
+            jr[4 * v + 3] = q4.w;
+        }
+    };
+    if constexpr (MODE == NBODY_PLAIN) {
+#pragma unroll 8
+        for (int jj = 0; jj < JT; ++jj) {
+            float jr[W];
+            read(jj, jr);
+#pragma unroll
+            for (int k = 0; k < IPL; ++k) Op::template pair<FULL>(jr, is[k], eps2, hs[k]);
+        }
+    } else {
+        for (int jb = 0; jb < JT; jb += kBlockJ) {
+            float bs[IPL][NO];
+#pragma unroll
+            for (int k = 0; k < IPL; ++k)
+#pragma unroll
+                for (int c = 0; c < NO; ++c) bs[k][c] = -0.0f;
+#pragma unroll
+            for (int jj = 0; jj < kBlockJ; ++jj) {
+                float jr[W];
+                read(jb + jj, jr);
+#pragma unroll
+                for (int k = 0; k < IPL; ++k) Op::template pair<FULL>(jr, is[k], eps2, bs[k]);
+            }
+#pragma unroll
+            for (int k = 0; k < IPL; ++k)
+#pragma unroll
+                for (int c = 0; c < NO; ++c) {
+                    if constexpr (MODE == NBODY_COMP)
+                        two_sum(hs[k][c], ls[k][c], bs[k][c]);
+                    else
+                        ds[k][c] += (double)bs[k][c];
+                }
+        }
+    }
+}
+
+template <class Op, int IPL, int JT, int MODE, bool FULL>
+__global__ __launch_bounds__(kTPB) void tile_kernel(typename Op::Args a) {
+    constexpr int W = Op::kJWords;
+    constexpr int NO = Op::kOut;
+    constexpr int LPT = (JT + kTPB - 1) / kTPB;  // j-records staged per lane
+    static_assert(W % 4 == 0, "j-records are whole float4s");
+    __shared__ float4 tile[2][JT * (W / 4)];
+
+    const int tid = threadIdx.x;
+    const int n = a.n;
+    const int ibase = blockIdx.x * (kTPB * IPL);
+    const float eps2 = a.eps2;
+
+    typename Op::IState is[IPL];
+#pragma unroll
+    for (int k = 0; k < IPL; ++k) {
+        int i = ibase + k * kTPB + tid;
+        is[k] = Op::load_i(a, i < n ? i : n - 1);
+    }
+
+    float hs[IPL][NO], ls[IPL][NO];
+    double ds[IPL][NO];
+#pragma unroll
+    for (int k = 0; k < IPL; ++k)
+#pragma unroll
+        for (int c = 0; c < NO; ++c) {
+            hs[k][c] = 0.0f;
+            ls[k][c] = 0.0f;
+            ds[k][c] = 0.0;
+        }
+
+    const int j0 = blockIdx.y * a.seg_len;
+    const int j1 = min(j0 + a.seg_len, n);
+    const int ntiles = j1 > j0 ? (j1 - j0 + JT - 1) / JT : 0;
+
+    float stage[LPT][W];
+    auto fetch = [&](int t) {
+#pragma unroll
+        for (int q = 0; q < LPT; ++q) {
+            const int jj = q * kTPB + tid;
+            const int j = j0 + t * JT + jj;
+            if (jj < JT) {
+                if (j < j1)
+                    Op::load_j(a, j, stage[q]);
+                else
+                    Op::pad_j(stage[q]);
+            }
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < LPT; ++q) {
+            const int jj = q * kTPB + tid;
+            if (jj < JT)
+#pragma unroll
+                for (int v = 0; v < W / 4; ++v)
+                    tile[buf][jj * (W / 4) + v] =
+                        make_float4(stage[q][4 * v], stage[q][4 * v + 1], stage[q][4 * v + 2],
+                                    stage[q][4 * v + 3]);
+        }
+    };
+
+    if (ntiles > 0) {
+        fetch(0);
+        store(0);
+    }
+    __syncthreads();
+    for (int t = 0; t < ntiles; ++t) {
+        const int buf = t & 1;
+        if (t + 1 < ntiles) fetch(t + 1);
+        tile_pass<Op, IPL, JT, MODE, FULL>(tile[buf], is, eps2, hs, ls, ds);
+        if (t + 1 < ntiles) store(buf ^ 1);
+        __syncthreads();
+    }
+
+    // Partial sums of this (i-tile, segment): planes [seg][word][npad].
+    const size_t plane = (size_t)a.npad;
+    const size_t seg = blockIdx.y;
+#pragma unroll
+    for (int k = 0; k < IPL; ++k) {
+        const size_t i = (size_t)ibase + k * kTPB + tid;
+        if constexpr (MODE == NBODY_FP64RED) {
+            double *p = static_cast<double *>(a.part) + seg * NO * plane + i;
+#pragma unroll
+            for (int c = 0; c < NO; ++c) p[c * plane] = ds[k][c];
+        } else if constexpr (MODE == NBODY_COMP) {
+            float *p = static_cast<float *>(a.part) + seg * 2 * NO * plane + i;
+#pragma unroll
+            for (int c = 0; c < NO; ++c) {
+                p[c * plane] = hs[k][c];
+                p[(NO + c) * plane] = ls[k][c];
+            }
+        } else {
+            float *p = static_cast<float *>(a.part) + seg * NO * plane + i;
+#pragma unroll
+            for (int c = 0; c < NO; ++c) p[c * plane] = hs[k][c];
+        }
+    }
+}
+
+// Fixed-order sum of the segment partials of particle i (FP64 for FP64RED/COMP,
+// FP32 for PLAIN, returned widened), in r[0 .. NO).
+template <int NO, int MODE>
+__device__ __forceinline__ void sum_partials(const void *part, int nseg, size_t plane, int i,
+                                             double (&r)[NO]) {
+    if constexpr (MODE == NBODY_PLAIN) {
+        float f[NO];
+#pragma unroll
+        for (int c = 0; c < NO; ++c) f[c] = 0.0f;
+        const float *p = static_cast<const float *>(part) + i;
+        for (int s = 0; s < nseg; ++s)
+#pragma unroll
+            for (int c = 0; c < NO; ++c) f[c] = f[c] + p[((size_t)s * NO + c) * plane];
+#pragma unroll
+        for (int c = 0; c < NO; ++c) r[c] = (double)f[c];
+    } else if constexpr (MODE == NBODY_COMP) {
+        const float *p = static_cast<const float *>(part) + i;
+#pragma unroll
+        for (int c = 0; c < NO; ++c) r[c] = 0.0;
+        for (int s = 0; s < nseg; ++s)
+#pragma unroll
+            for (int c = 0; c < NO; ++c) {
+                r[c] += (double)p[((size_t)s * 2 * NO + c) * plane];
+                r[c] += (double)p[((size_t)s * 2 * NO + NO + c) * plane];
+            }
+    } else {
+        const double *p = static_cast<const double *>(part) + i;
+#pragma unroll
+        for (int c = 0; c < NO; ++c) r[c] = 0.0;
+        for (int s = 0; s < nseg; ++s)
+#pragma unroll
+            for (int c = 0; c < NO; ++c) r[c] += p[((size_t)s * NO + c) * plane];
+    }
+}
+
+// Launch-shape dispatch over the template parameters.
+template <class Op>
+using TileFn = void (*)(typename Op::Args);
+
+template <class Op, int IPL, int JT, int MODE>
+TileFn<Op> pick_full(bool full) {
+    return full ? tile_kernel<Op, IPL, JT, MODE, true> : tile_kernel<Op, IPL, JT, MODE, false>;
+}
+
+template <class Op, int IPL, int JT>
+TileFn<Op> pick_mode(int mode, bool full) {
+    switch (mode) {
+        case NBODY_PLAIN: return pick_full<Op, IPL, JT, NBODY_PLAIN>(full);
+        case NBODY_FP64RED: return pick_full<Op, IPL, JT, NBODY_FP64RED>(full);
+        case NBODY_COMP: return pick_full<Op, IPL, JT, NBODY_COMP>(full);
+    }
+    return nullptr;
+}
+
+template <class Op, int IPL>
+TileFn<Op> pick_jt(int jt, int mode, bool full) {
+    switch (jt) {
+        case 64: return pick_mode<Op, IPL, 64>(mode, full);
+        case 128: return pick_mode<Op, IPL, 128>(mode, full);
+        case 256: return pick_mode<Op, IPL, 256>(mode, full);
+        case 512: return pick_mode<Op, IPL, 512>(mode, full);
+    }
+    return nullptr;
+}
+
+template <class Op>
+TileFn<Op> pick_tile(int ipl, int jt, int mode, bool full) {
+    switch (ipl) {
+        case 1: return pick_jt<Op, 1>(jt, mode, full);
+        case 2: return pick_jt<Op, 2>(jt, mode, full);
+        case 4: return pick_jt<Op, 4>(jt, mode, full);
+        case 8: return pick_jt<Op, 8>(jt, mode, full);
+    }
+    return nullptr;
+}
+
+}  // namespace engine
+}  // namespace nbody

@@ -20,7 +20,12 @@ int bucket(int64_t n) {
 }
 
 TuneEntry builtin(int kernel, int64_t n) {
-    (void)kernel;
+    if (kernel == KERNEL_VJP) {
+        // The adjoint keeps 8 i-values and 4 accumulators (x3 when blocked) per
+        // i-particle; two per lane keep it within about 100 VGPRs.
+        if (n >= 8192) return {2, 128, 0};
+        return {1, 128, 0};
+    }
     // More i-particles per lane amortise each LDS read over more pair terms, but
     // leave fewer i-tiles to spread over the compute units for small n.
     if (n >= 32768) return {4, 256, 0};

@@ -147,3 +147,19 @@ def test_graph_create_rejects_invalid_arguments():
     assert st == _lib.NBODY_EINVAL
     assert lib.nbody_graph_launch(None, None) == _lib.NBODY_EINVAL
     lib.nbody_graph_destroy(None)
+
+
+def test_vjp_and_adjoint_reject_invalid_arguments():
+    o = _lib.nbody_opts_default()
+    for f in (_lib.nbody_force_vjp, _lib.nbody_force_vjp_f64):
+        assert f(-1, FAKE, FAKE, 0.1, FAKE, None, FAKE, None, o, None, check=False) == _lib.NBODY_EINVAL
+        assert f(10, FAKE, FAKE, 0.1, None, None, FAKE, None, o, None, check=False) == _lib.NBODY_EINVAL
+        assert f(10, FAKE, FAKE, 0.1, FAKE, None, None, None, o, None, check=False) == _lib.NBODY_EINVAL
+        assert f(10, FAKE, FAKE, -0.1, FAKE, None, FAKE, None, o, None, check=False) == _lib.NBODY_EINVAL
+        assert f(10, FAKE, FAKE, 0.1, FAKE + 4, None, FAKE, None, o, None, check=False) == _lib.NBODY_EINVAL
+        assert f(0, None, None, 0.1, None, None, None, None, o, None, check=False) == _lib.NBODY_OK
+    adj = _lib.nbody_leapfrog_adjoint
+    assert adj(10, FAKE, FAKE, 0.1, 0.01, -1, FAKE, FAKE, None, o, None, check=False) == _lib.NBODY_EINVAL
+    assert adj(10, FAKE, FAKE, 0.1, float("nan"), 2, FAKE, FAKE, None, o, None, check=False) == _lib.NBODY_EINVAL
+    assert adj(10, FAKE, FAKE, 0.1, 0.01, 2, FAKE, None, None, o, None, check=False) == _lib.NBODY_EINVAL
+    assert adj(0, None, None, 0.1, 0.01, 2, None, None, None, o, None, check=False) == _lib.NBODY_OK
