@@ -183,6 +183,52 @@ NBODY_API nbody_status nbody_leapfrog_adjoint(int64_t n, const double *traj, con
                                               double *vbar, double *mbar, const nbody_opts *opts,
                                               void *stream);
 
+/* ------------------------------------------------------------------------------
+ * Ragged batches: nsys independent systems stored back to back in one set of arrays;
+ * system k owns the particles [offsets[k], offsets[k+1]) and interacts only with
+ * itself (eq. (1) within each system), with its own softening eps[k].
+ *
+ * A plan is built once from the HOST array offsets (int64, nsys + 1 entries,
+ * offsets[0] = 0, non-decreasing, total < 2^30; empty systems allowed).  It cuts every
+ * system into work items (an i-tile against a j-range), sorts them by decreasing
+ * cost, and owns the device tables, the partial-sum scratch and the ticket counter of
+ * the persistent kernel that runs them - so every call with a plan allocates nothing
+ * and can be captured in a graph.  Calls with the same plan must not overlap in time
+ * (they share its scratch).  opts: precision, centre (NONE or SYSTEM), ipl, jtile;
+ * self_pot must be 0 and workspace NULL.  The plan belongs to the current device.
+ * ---------------------------------------------------------------------------- */
+typedef struct nbody_plan nbody_plan;
+NBODY_API nbody_status nbody_plan_create_batched(int32_t nsys, const int64_t *h_offsets,
+                                                 const nbody_opts *opts, nbody_plan **out);
+NBODY_API void nbody_plan_destroy(nbody_plan *plan);
+/* info[0..8): nsys, total particles, work items, persistent blocks, pairs (sum N_k^2),
+ * pairs including tile padding, ipl, jtile. */
+NBODY_API nbody_status nbody_plan_info(const nbody_plan *plan, int64_t *info);
+
+/* Forces and potentials of every system.  pos float [3][total], mass float [total],
+ * eps float [nsys] (device), acc double [3][total], pot double [total] or NULL. */
+NBODY_API nbody_status nbody_force_batched(const nbody_plan *plan, const float *pos,
+                                           const float *mass, const float *eps, double *acc,
+                                           double *pot, void *stream);
+/* As nbody_force_batched with FP64 positions (converted per system relative to its
+ * FP64 mean position when the plan's centre is NBODY_CENTRE_SYSTEM). */
+NBODY_API nbody_status nbody_force_batched_f64(const nbody_plan *plan, const double *pos64,
+                                               const float *mass, const float *eps, double *acc,
+                                               double *pot, void *stream);
+/* nsteps KDK leapfrog steps of every system at once (as nbody_leapfrog). */
+NBODY_API nbody_status nbody_leapfrog_batched(const nbody_plan *plan, double *pos64,
+                                              double *vel64, const float *mass, const float *eps,
+                                              double dt, int32_t nsteps, double *acc, double *pot,
+                                              int32_t flags, void *stream);
+/* HIP graph of nsteps batched leapfrog steps (acc must hold a(pos64) when launched);
+ * launched and destroyed with nbody_graph_launch / nbody_graph_destroy. */
+NBODY_API nbody_status nbody_graph_create_leapfrog_batched(const nbody_plan *plan, double *pos64,
+                                                           double *vel64, const float *mass,
+                                                           const float *eps, double dt,
+                                                           int32_t nsteps, double *acc,
+                                                           double *pot, void *stream,
+                                                           nbody_graph **out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -80,6 +80,14 @@ SIGNATURES = {
     "nbody_force_vjp": (_I32, [_I64, _P, _P, _F, _P, _P, _P, _P, _OPTS, _P]),
     "nbody_force_vjp_f64": (_I32, [_I64, _P, _P, _F, _P, _P, _P, _P, _OPTS, _P]),
     "nbody_leapfrog_adjoint": (_I32, [_I64, _P, _P, _F, _D, _I32, _P, _P, _P, _OPTS, _P]),
+    "nbody_plan_create_batched": (_I32, [_I32, ctypes.POINTER(_I64), _OPTS, ctypes.POINTER(_P)]),
+    "nbody_plan_destroy": (None, [_P]),
+    "nbody_plan_info": (_I32, [_P, ctypes.POINTER(_I64)]),
+    "nbody_force_batched": (_I32, [_P, _P, _P, _P, _P, _P, _P]),
+    "nbody_force_batched_f64": (_I32, [_P, _P, _P, _P, _P, _P, _P]),
+    "nbody_leapfrog_batched": (_I32, [_P, _P, _P, _P, _P, _D, _I32, _P, _P, _I32, _P]),
+    "nbody_graph_create_leapfrog_batched": (_I32, [_P, _P, _P, _P, _P, _D, _I32, _P, _P, _P,
+                                                   ctypes.POINTER(_P)]),
 }
 
 NBODY_LF_INIT_ACC = 1
@@ -192,3 +200,49 @@ def nbody_leapfrog_adjoint(n, traj, mass, eps, dt, nsteps, xbar, vbar, mbar, opt
     st = load().nbody_leapfrog_adjoint(n, traj, mass, eps, dt, nsteps, xbar, vbar, mbar,
                                        _opt_ref(opts), stream)
     return _check(st, "nbody_leapfrog_adjoint") if check else st
+
+
+def nbody_plan_create_batched(nsys, offsets, opts):
+    """``offsets``: sequence of nsys + 1 host integers.  Returns the plan handle."""
+    arr = (_I64 * (nsys + 1))(*[int(v) for v in offsets])
+    h = ctypes.c_void_p()
+    st = load().nbody_plan_create_batched(nsys, arr, _opt_ref(opts), ctypes.byref(h))
+    _check(st, "nbody_plan_create_batched")
+    return h.value
+
+
+def nbody_plan_destroy(plan):
+    load().nbody_plan_destroy(plan)
+
+
+def nbody_plan_info(plan):
+    info = (_I64 * 8)()
+    _check(load().nbody_plan_info(plan, info), "nbody_plan_info")
+    keys = ("nsys", "total", "items", "blocks", "pairs", "padded_pairs", "ipl", "jtile")
+    return dict(zip(keys, [int(v) for v in info]))
+
+
+def nbody_force_batched(plan, pos, mass, eps, acc, pot, stream, check=True):
+    st = load().nbody_force_batched(plan, pos, mass, eps, acc, pot, stream)
+    return _check(st, "nbody_force_batched") if check else st
+
+
+def nbody_force_batched_f64(plan, pos64, mass, eps, acc, pot, stream, check=True):
+    st = load().nbody_force_batched_f64(plan, pos64, mass, eps, acc, pot, stream)
+    return _check(st, "nbody_force_batched_f64") if check else st
+
+
+def nbody_leapfrog_batched(plan, pos64, vel64, mass, eps, dt, nsteps, acc, pot, flags, stream,
+                           check=True):
+    st = load().nbody_leapfrog_batched(plan, pos64, vel64, mass, eps, dt, nsteps, acc, pot, flags,
+                                       stream)
+    return _check(st, "nbody_leapfrog_batched") if check else st
+
+
+def nbody_graph_create_leapfrog_batched(plan, pos64, vel64, mass, eps, dt, nsteps, acc, pot,
+                                        stream):
+    h = ctypes.c_void_p()
+    st = load().nbody_graph_create_leapfrog_batched(plan, pos64, vel64, mass, eps, dt, nsteps,
+                                                    acc, pot, stream, ctypes.byref(h))
+    _check(st, "nbody_graph_create_leapfrog_batched")
+    return h.value

@@ -11,8 +11,8 @@ import torch
 
 from . import _lib
 
-__all__ = ["make_opts", "force", "force_f64", "leapfrog", "LeapfrogGraph", "soa", "aos",
-           "stream_ptr"]
+__all__ = ["make_opts", "force", "force_f64", "leapfrog", "LeapfrogGraph", "BatchPlan", "soa",
+           "aos", "stream_ptr"]
 
 
 def make_opts(precision: str = "comp", centre: str = "system", self_pot: bool = False,
@@ -147,3 +147,75 @@ class LeapfrogGraph:
             self.close()
         except Exception:
             pass
+
+
+class BatchPlan:
+    """Plan for a ragged batch of independent systems (see ``nbody_plan_create_batched``).
+
+    ``offsets``: host sequence of ``nsys + 1`` integers; system k owns the particles
+    ``offsets[k]:offsets[k+1]`` of every ``[3, total]`` / ``[total]`` tensor.
+    """
+
+    def __init__(self, offsets, precision="comp", centre="system", ipl=0, jtile=0):
+        offsets = [int(v) for v in offsets]
+        self.nsys = len(offsets) - 1
+        self.total = offsets[-1] if offsets else 0
+        opts = make_opts(precision=precision, centre=centre, ipl=ipl, jtile=jtile)
+        self.handle = _lib.nbody_plan_create_batched(self.nsys, offsets, opts)
+
+    def info(self) -> dict:
+        return _lib.nbody_plan_info(self.handle)
+
+    def _out(self, dev, with_pot):
+        return (torch.empty((3, self.total), dtype=torch.float64, device=dev),
+                torch.empty(self.total, dtype=torch.float64, device=dev) if with_pot else None)
+
+    def force(self, pos, mass, eps, with_pot=True):
+        """FP32 positions ``[3, total]``, masses ``[total]``, per-system eps ``[nsys]``."""
+        acc, pot = self._out(pos.device, with_pot)
+        _lib.nbody_force_batched(self.handle, pos.data_ptr(), mass.data_ptr(), eps.data_ptr(),
+                                 acc.data_ptr(), pot.data_ptr() if pot is not None else None,
+                                 stream_ptr())
+        return acc, pot
+
+    def force_f64(self, pos64, mass, eps, with_pot=True):
+        acc, pot = self._out(pos64.device, with_pot)
+        _lib.nbody_force_batched_f64(self.handle, pos64.data_ptr(), mass.data_ptr(),
+                                     eps.data_ptr(), acc.data_ptr(),
+                                     pot.data_ptr() if pot is not None else None, stream_ptr())
+        return acc, pot
+
+    def leapfrog(self, pos64, vel64, mass, eps, dt, nsteps, acc=None, init=True, with_pot=False):
+        if acc is None:
+            acc = torch.empty((3, self.total), dtype=torch.float64, device=pos64.device)
+        pot = (torch.empty(self.total, dtype=torch.float64, device=pos64.device)
+               if with_pot else None)
+        _lib.nbody_leapfrog_batched(self.handle, pos64.data_ptr(), vel64.data_ptr(),
+                                    mass.data_ptr(), eps.data_ptr(), float(dt), int(nsteps),
+                                    acc.data_ptr(), pot.data_ptr() if pot is not None else None,
+                                    _lib.NBODY_LF_INIT_ACC if init else 0, stream_ptr())
+        return acc, pot
+
+    def graph(self, pos64, vel64, mass, eps, dt, nsteps, acc, pot=None):
+        """A replayable graph of ``nsteps`` batched KDK steps on these tensors."""
+        return _BatchGraph(self, pos64, vel64, mass, eps, dt, nsteps, acc, pot)
+
+    def close(self):
+        if self.handle:
+            _lib.nbody_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class _BatchGraph(LeapfrogGraph):
+    def __init__(self, plan, pos64, vel64, mass, eps, dt, nsteps, acc, pot):  # noqa: D401
+        self._keep = (plan, pos64, vel64, mass, eps, acc, pot)
+        self.handle = _lib.nbody_graph_create_leapfrog_batched(
+            plan.handle, pos64.data_ptr(), vel64.data_ptr(), mass.data_ptr(), eps.data_ptr(),
+            float(dt), int(nsteps), acc.data_ptr(), pot.data_ptr() if pot is not None else None,
+            stream_ptr())

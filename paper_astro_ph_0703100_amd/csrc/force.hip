@@ -1,53 +1,9 @@
-// Gravity pipeline for the tile engine: softened accelerations and potentials,
-// eq. (1) of the paper, plus the FP64 finalize and the FP64-position pre-pass.
-#include "tile_engine.h"
+// Force evaluation of one system: the gravity pipeline on the tile engine (grid
+// launch), the FP64 finalize, and the FP64-position pre-pass (centre, conversion).
+#include "gravity.h"
 
 namespace nbody {
 namespace {
-
-struct Gravity {
-    static constexpr int kJWords = 4;  // x, y, z, m
-    static constexpr int kOut = 4;     // ax, ay, az, phi
-    using Args = PairArgs;
-    struct IState {
-        float x, y, z;
-    };
-    static __device__ __forceinline__ IState load_i(const Args &a, int i) {
-        return {a.x[i], a.y[i], a.z[i]};
-    }
-    static __device__ __forceinline__ void load_j(const Args &a, int j, float (&r)[4]) {
-        r[0] = a.x[j];
-        r[1] = a.y[j];
-        r[2] = a.z[j];
-        r[3] = a.m[j];
-    }
-    // A massless particle at the origin adds exactly zero.
-    static __device__ __forceinline__ void pad_j(float (&r)[4]) { r[0] = r[1] = r[2] = r[3] = 0.0f; }
-
-    // One softened pair term: separation x_j - x_i, s^2 = |d|^2 + eps^2 as an FMA chain,
-    // 1/s from the hardware reciprocal square root (about 1 ulp); a += m d / s^3 and
-    // phi -= m / s with m / s rounded on its own.  13 VALU operations and one
-    // v_rsq_f32.  For j == i the separation is exactly zero, so that pair adds nothing
-    // to a and adds -fl(m_i rsq(eps^2)) to phi, which the finalize removes.
-    template <bool POT>
-    static __device__ __forceinline__ void pair(const float *j, const IState &i, float eps2,
-                                                float (&acc)[4]) {
-        const float dx = j[0] - i.x;
-        const float dy = j[1] - i.y;
-        const float dz = j[2] - i.z;
-        float s2 = __builtin_fmaf(dx, dx, eps2);
-        s2 = __builtin_fmaf(dy, dy, s2);
-        s2 = __builtin_fmaf(dz, dz, s2);
-        const float ri = __builtin_amdgcn_rsqf(s2);
-        const float mri = j[3] * ri;
-        const float ri2 = ri * ri;
-        const float mri3 = mri * ri2;
-        acc[0] = __builtin_fmaf(mri3, dx, acc[0]);
-        acc[1] = __builtin_fmaf(mri3, dy, acc[1]);
-        acc[2] = __builtin_fmaf(mri3, dz, acc[2]);
-        if (POT) acc[3] = acc[3] - mri;
-    }
-};
 
 // Fixed-order sum of the segment partials (PLAIN in FP32, the other modes in FP64),
 // then removal of the j == i potential term fl(m_i * rsq(eps^2)), recomputed with the

@@ -6,17 +6,11 @@
 // the second kick is fused into the finalize.  a(x) carries over from one step to the
 // next, so each step costs one force evaluation.
 #include <cmath>
+#include <functional>
 #include <new>
 
 #include "nbody_internal.h"
 #include "tuning.h"
-
-struct nbody_graph {
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    void *workspace = nullptr;
-    int device = 0;
-};
 
 namespace nbody {
 namespace {
@@ -60,6 +54,31 @@ nbody_status enqueue_steps(int64_t n, double *x, double *v, const float *m, floa
 }
 
 }  // namespace
+
+nbody_status capture_graph(nbody_graph *g, const std::function<nbody_status(hipStream_t)> &body) {
+    // Capture on a private stream (the null stream cannot be captured); the launches
+    // are recorded, not run.
+    hipStream_t cs = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_error(e, "hipStreamCreate");
+    if ((e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
+        (void)hipStreamDestroy(cs);
+        return hip_error(e, "hipStreamBeginCapture");
+    }
+    nbody_status st = body(cs);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(cs, &graph);
+    (void)hipStreamDestroy(cs);
+    g->graph = graph;
+    if (st) return st;
+    if (e != hipSuccess) return hip_error(e, "hipStreamEndCapture");
+    if ((e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0)) != hipSuccess) {
+        g->exec = nullptr;
+        return hip_error(e, "hipGraphInstantiate");
+    }
+    return NBODY_OK;
+}
+
 }  // namespace nbody
 
 using namespace nbody;
@@ -121,27 +140,12 @@ nbody_status nbody_graph_create_leapfrog(int64_t n, double *pos64, double *vel64
     o.workspace = g->workspace;
     o.workspace_bytes = need;
 
-    // Capture on a private stream (the null stream cannot be captured); the steps'
-    // launches are recorded, not run.
-    hipStream_t cs = nullptr;
-    if ((e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)) != hipSuccess)
-        return fail(hip_error(e, "hipStreamCreate"));
-    if ((e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
-        (void)hipStreamDestroy(cs);
-        return fail(hip_error(e, "hipStreamBeginCapture"));
-    }
-    st = enqueue_steps(n, pos64, vel64, mass, eps, dt, nsteps, acc, pot, nullptr, false, o, cfg,
-                       f64_scratch_layout(g->workspace, n, cfg, o.precision), cs);
-    hipGraph_t graph = nullptr;
-    e = hipStreamEndCapture(cs, &graph);
-    (void)hipStreamDestroy(cs);
-    g->graph = graph;
+    const F64Scratch lay = f64_scratch_layout(g->workspace, n, cfg, o.precision);
+    st = capture_graph(g, [&](hipStream_t cs) {
+        return enqueue_steps(n, pos64, vel64, mass, eps, dt, nsteps, acc, pot, nullptr, false, o,
+                             cfg, lay, cs);
+    });
     if (st) return fail(st);
-    if (e != hipSuccess) return fail(hip_error(e, "hipStreamEndCapture"));
-    if ((e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0)) != hipSuccess) {
-        g->exec = nullptr;
-        return fail(hip_error(e, "hipGraphInstantiate"));
-    }
     *out = g;
     return NBODY_OK;
 }

@@ -5,9 +5,18 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <functional>
 #include <string>
 
 #include "nbody.h"
+
+// A captured HIP graph and the scratch memory it owns (if any).
+struct nbody_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void *workspace = nullptr;
+    int device = 0;
+};
 
 namespace nbody {
 
@@ -42,6 +51,46 @@ struct PairArgs {
     float eps2;   // fp32(eps^2)
     void *part;   // partial sums [nseg][words][npad]
     int npad;
+};
+
+// One work item of a ragged batch: an i-tile of one system against a j-range of the
+// same system.  Indices are global (into the concatenated arrays).
+struct BatchItem {
+    int32_t sys;    // system index
+    int32_t i0;     // first i of the tile
+    int32_t ni;     // i's in the tile (<= 256 * IPL)
+    int32_t j0;     // first j of the range
+    int32_t nj;     // j's in the range
+    int32_t col0;   // column of i0 in the system's partial planes (i0 - offset)
+    int64_t part;   // word offset of this (system, segment)'s partial planes
+    int32_t npad;   // plane stride of the system (its i-tiles * 256 * IPL)
+    int32_t pad_;
+};
+
+// Work queue of a persistent batched launch.
+struct BatchSched {
+    const BatchItem *items;
+    int nitems;
+    unsigned int *counter;  // ticket, reset to 0 before every launch
+    const float *eps;       // per-system softening [nsys]
+    void *part;             // partial-sum words
+};
+
+// Arguments of the batched FP64 reduction (per particle, looked up by system).
+struct BatchFinalizeArgs {
+    const void *part;
+    int64_t total;
+    const int32_t *sys_of;     // [total] system of each particle
+    const int64_t *offsets;    // [nsys + 1]
+    const int64_t *part_base;  // [nsys] word offset of each system's planes
+    const int32_t *npad;       // [nsys]
+    const int32_t *nseg;       // [nsys]
+    const float *eps;          // [nsys]
+    const float *m;
+    double *acc;               // [3][total]
+    double *pot;               // [total] or nullptr
+    double *kick_v;            // [3][total] or nullptr
+    double kick_h;
 };
 
 // Arguments of the FP64 reduction of the partial sums.
@@ -122,6 +171,10 @@ nbody_status force_f64_core(int64_t n, const double *pos64, const float *mass, f
                             double *acc, double *pot, const nbody_opts &o, const TileCfg &cfg,
                             const F64Scratch &ws, double *kick_v, double kick_h, hipStream_t s);
 
+// Records the launches `body` enqueues on a capture stream into g->graph and
+// instantiates g->exec (integrate.cpp).
+nbody_status capture_graph(nbody_graph *g, const std::function<nbody_status(hipStream_t)> &body);
+
 // Device properties cached per device.
 struct DeviceInfo {
     int cus = 256;
@@ -150,6 +203,15 @@ nbody_status launch_axpy_f64(int64_t count, double *y, double alpha, const doubl
 // Reverse of one leapfrog step's drift and first kick: vbar += dt * xbar; abar = h * vbar.
 nbody_status launch_adj_drift_kick(int64_t count, double *vbar, const double *xbar, double *abar,
                                    double dt, double h, hipStream_t s);
+// Ragged batches (batched.hip).
+nbody_status batched_pair_kernel(int ipl, int jt, int precision, bool with_pot, const void **fn);
+nbody_status launch_batched_pair(int ipl, int jt, int precision, bool with_pot, int grid,
+                                 const PairArgs &a, const BatchSched &sc, hipStream_t s);
+nbody_status launch_batched_finalize(int precision, const BatchFinalizeArgs &a, hipStream_t s);
+nbody_status launch_system_centres(int nsys, const int64_t *offsets, int64_t total,
+                                   const double *pos64, double *centre, hipStream_t s);
+nbody_status launch_batched_convert(int64_t total, const double *pos64, const int32_t *sys_of,
+                                    const double *centre, float *pos32, hipStream_t s);
 // Adjoint pair kernel and its FP64 finalize (vjp.hip).
 nbody_status launch_vjp(const TileCfg &cfg, int precision, const VjpArgs &a, bool with_mass,
                         hipStream_t s);

@@ -105,24 +105,25 @@ __device__ __forceinline__ void tile_pass(const float4 *tl, const typename Op::I
     }
 }
 
+// One block's work: the i-tile [i0, i0 + ni) (ni <= 256 * IPL) against the j-range
+// [j0, j0 + nj), partial sums written to planes out[word * plane + col0 + lane-slot].
+// `tile` is the block's LDS staging area; every lane of the block must call this
+// with the same arguments (it contains barriers).
 template <class Op, int IPL, int JT, int MODE, bool FULL>
-__global__ __launch_bounds__(kTPB) void tile_kernel(typename Op::Args a) {
+__device__ __forceinline__ void block_work(const typename Op::Args &a, float4 (*tile)[JT * (Op::kJWords / 4)],
+                                           int i0, int ni, int j0, int nj, float eps2, void *out,
+                                           size_t plane, size_t col0) {
     constexpr int W = Op::kJWords;
     constexpr int NO = Op::kOut;
     constexpr int LPT = (JT + kTPB - 1) / kTPB;  // j-records staged per lane
     static_assert(W % 4 == 0, "j-records are whole float4s");
-    __shared__ float4 tile[2][JT * (W / 4)];
-
     const int tid = threadIdx.x;
-    const int n = a.n;
-    const int ibase = blockIdx.x * (kTPB * IPL);
-    const float eps2 = a.eps2;
 
     typename Op::IState is[IPL];
 #pragma unroll
     for (int k = 0; k < IPL; ++k) {
-        int i = ibase + k * kTPB + tid;
-        is[k] = Op::load_i(a, i < n ? i : n - 1);
+        const int r = k * kTPB + tid;
+        is[k] = Op::load_i(a, i0 + (r < ni ? r : ni - 1));
     }
 
     float hs[IPL][NO], ls[IPL][NO];
@@ -136,9 +137,8 @@ __global__ __launch_bounds__(kTPB) void tile_kernel(typename Op::Args a) {
             ds[k][c] = 0.0;
         }
 
-    const int j0 = blockIdx.y * a.seg_len;
-    const int j1 = min(j0 + a.seg_len, n);
-    const int ntiles = j1 > j0 ? (j1 - j0 + JT - 1) / JT : 0;
+    const int j1 = j0 + nj;
+    const int ntiles = nj > 0 ? (nj + JT - 1) / JT : 0;
 
     float stage[LPT][W];
     auto fetch = [&](int t) {
@@ -180,28 +180,68 @@ __global__ __launch_bounds__(kTPB) void tile_kernel(typename Op::Args a) {
         __syncthreads();
     }
 
-    // Partial sums of this (i-tile, segment): planes [seg][word][npad].
-    const size_t plane = (size_t)a.npad;
-    const size_t seg = blockIdx.y;
 #pragma unroll
     for (int k = 0; k < IPL; ++k) {
-        const size_t i = (size_t)ibase + k * kTPB + tid;
+        const size_t i = col0 + k * kTPB + tid;
         if constexpr (MODE == NBODY_FP64RED) {
-            double *p = static_cast<double *>(a.part) + seg * NO * plane + i;
+            double *p = static_cast<double *>(out) + i;
 #pragma unroll
             for (int c = 0; c < NO; ++c) p[c * plane] = ds[k][c];
         } else if constexpr (MODE == NBODY_COMP) {
-            float *p = static_cast<float *>(a.part) + seg * 2 * NO * plane + i;
+            float *p = static_cast<float *>(out) + i;
 #pragma unroll
             for (int c = 0; c < NO; ++c) {
                 p[c * plane] = hs[k][c];
                 p[(NO + c) * plane] = ls[k][c];
             }
         } else {
-            float *p = static_cast<float *>(a.part) + seg * NO * plane + i;
+            float *p = static_cast<float *>(out) + i;
 #pragma unroll
             for (int c = 0; c < NO; ++c) p[c * plane] = hs[k][c];
         }
+    }
+}
+
+// Words (4 bytes) of partial sums per output, i-particle and segment.
+template <int MODE>
+constexpr int words_per_out() {
+    return MODE == NBODY_PLAIN ? 1 : 2;
+}
+
+// Grid launch: blockIdx.x = i-tile, blockIdx.y = j-segment of a.seg_len j's.  Partial
+// planes [seg][word][npad].
+template <class Op, int IPL, int JT, int MODE, bool FULL>
+__global__ __launch_bounds__(kTPB) void tile_kernel(typename Op::Args a) {
+    __shared__ float4 tile[2][JT * (Op::kJWords / 4)];
+    const int i0 = blockIdx.x * (kTPB * IPL);
+    const int ni = min(kTPB * IPL, a.n - i0);
+    const int j0 = blockIdx.y * a.seg_len;
+    const int nj = max(0, min(a.seg_len, a.n - j0));
+    const size_t plane = (size_t)a.npad;
+    constexpr int WO = Op::kOut * words_per_out<MODE>();
+    void *out = static_cast<float *>(a.part) + (size_t)blockIdx.y * WO * plane;
+    block_work<Op, IPL, JT, MODE, FULL>(a, tile, i0, ni, j0, nj, a.eps2, out, plane, (size_t)i0);
+}
+
+// Persistent launch over a list of work items (ragged batches of independent
+// systems).  Each block takes the next item from an atomic ticket until the list is
+// exhausted; items are sorted by decreasing cost so the tail is short.  Every item
+// writes its own partial slots, so results do not depend on which block ran it.
+template <class Op, int IPL, int JT, int MODE, bool FULL>
+__global__ __launch_bounds__(kTPB) void persistent_kernel(typename Op::Args a, BatchSched sc) {
+    __shared__ float4 tile[2][JT * (Op::kJWords / 4)];
+    __shared__ int s_item;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = (int)atomicAdd(sc.counter, 1u);
+        __syncthreads();
+        const int it = s_item;
+        __syncthreads();  // all lanes hold `it` before lane 0 can overwrite s_item
+        if (it >= sc.nitems) break;
+        const BatchItem w = sc.items[it];
+        const float e = sc.eps[w.sys];
+        void *out = static_cast<float *>(sc.part) + w.part;
+        block_work<Op, IPL, JT, MODE, FULL>(a, tile, w.i0, w.ni, w.j0, w.nj, e * e, out,
+                                            (size_t)w.npad, (size_t)w.col0);
     }
 }
 
@@ -277,6 +317,46 @@ TileFn<Op> pick_tile(int ipl, int jt, int mode, bool full) {
         case 2: return pick_jt<Op, 2>(jt, mode, full);
         case 4: return pick_jt<Op, 4>(jt, mode, full);
         case 8: return pick_jt<Op, 8>(jt, mode, full);
+    }
+    return nullptr;
+}
+
+template <class Op>
+using PersistFn = void (*)(typename Op::Args, BatchSched);
+
+template <class Op, int IPL, int JT, int MODE>
+PersistFn<Op> ppick_full(bool full) {
+    return full ? persistent_kernel<Op, IPL, JT, MODE, true> : persistent_kernel<Op, IPL, JT, MODE, false>;
+}
+
+template <class Op, int IPL, int JT>
+PersistFn<Op> ppick_mode(int mode, bool full) {
+    switch (mode) {
+        case NBODY_PLAIN: return ppick_full<Op, IPL, JT, NBODY_PLAIN>(full);
+        case NBODY_FP64RED: return ppick_full<Op, IPL, JT, NBODY_FP64RED>(full);
+        case NBODY_COMP: return ppick_full<Op, IPL, JT, NBODY_COMP>(full);
+    }
+    return nullptr;
+}
+
+template <class Op, int IPL>
+PersistFn<Op> ppick_jt(int jt, int mode, bool full) {
+    switch (jt) {
+        case 64: return ppick_mode<Op, IPL, 64>(mode, full);
+        case 128: return ppick_mode<Op, IPL, 128>(mode, full);
+        case 256: return ppick_mode<Op, IPL, 256>(mode, full);
+        case 512: return ppick_mode<Op, IPL, 512>(mode, full);
+    }
+    return nullptr;
+}
+
+template <class Op>
+PersistFn<Op> pick_persistent(int ipl, int jt, int mode, bool full) {
+    switch (ipl) {
+        case 1: return ppick_jt<Op, 1>(jt, mode, full);
+        case 2: return ppick_jt<Op, 2>(jt, mode, full);
+        case 4: return ppick_jt<Op, 4>(jt, mode, full);
+        case 8: return ppick_jt<Op, 8>(jt, mode, full);
     }
     return nullptr;
 }

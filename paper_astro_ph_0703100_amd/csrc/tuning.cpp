@@ -20,6 +20,11 @@ int bucket(int64_t n) {
 }
 
 TuneEntry builtin(int kernel, int64_t n) {
+    if (kernel == KERNEL_BATCHED) {
+        // n is the mean system size; small systems waste lanes of wide i-tiles.
+        if (n >= 2048) return {2, 128, 0};
+        return {1, 128, 0};
+    }
     if (kernel == KERNEL_VJP) {
         // The adjoint keeps 8 i-values and 4 accumulators (x3 when blocked) per
         // i-particle; two per lane keep it within about 100 VGPRs.

@@ -29,6 +29,13 @@ def to_dev(pos, mass):
             p32.T.astype(np.float64), m32.astype(np.float64))
 
 
+def pot_ok(pot, ref, m, eps, tol):
+    """|phi - phi_ref| <= tol |phi_ref| + 2 u m_i / eps: the j == i term m_i / eps sits in the
+    FP32 sums before its exact removal, so it adds up to about u m_i / eps of rounding."""
+    bound = tol * np.abs(ref) + 2 * 2.0 ** -24 * m / eps
+    return bool(np.all(np.abs(pot - ref) <= bound))
+
+
 def gpu_force(p, m, eps, **kw):
     acc, pot = api.force(p, m, eps, **kw)
     torch.cuda.synchronize()
@@ -62,7 +69,8 @@ def test_ragged_sizes(n):
             assert np.all(acc == 0) and np.all(pot == 0)
             continue
         ea, ep = rel_errors(acc, ra), rel_errors(pot, rp)
-        assert ea["rel_rms"] <= TOL[precision] and ep["rel_rms"] <= TOL[precision], (precision, ea, ep)
+        assert ea["rel_rms"] <= TOL[precision], (precision, ea)
+        assert pot_ok(pot, rp, m64, eps, 10 * TOL[precision]), (precision, ep)
 
 
 @pytest.mark.parametrize("ipl,jtile,nseg", [(1, 64, 1), (1, 512, 3), (2, 128, 7), (4, 256, 2),

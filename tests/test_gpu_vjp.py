@@ -171,7 +171,7 @@ def _rollout_grad(n, seed, eps, dt, steps, target_seed):
     xT, vT = autograd.rollout(xt, vt, mt, eps, dt, steps)
     loss = ((xT - yt) ** 2).sum() / n
     loss.backward()
-    return (x0, v0, m32, y, float(loss), xt.grad.cpu().numpy().T, vt.grad.cpu().numpy().T,
+    return (x0, v0, m32, y, float(loss.detach()), xt.grad.cpu().numpy().T, vt.grad.cpu().numpy().T,
             mt.grad.cpu().numpy())
 
 
