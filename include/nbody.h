@@ -229,6 +229,25 @@ NBODY_API nbody_status nbody_graph_create_leapfrog_batched(const nbody_plan *pla
                                                            double *pot, void *stream,
                                                            nbody_graph **out);
 
+/* ------------------------------------------------------------------------------
+ * Launch-shape table.  Shapes (i-particles per lane, j-tile, j-segments) are looked
+ * up per kernel, precision mode and size bucket floor(log2 n) (batched: mean system
+ * size); entries not set use built-in defaults; explicit opts fields override both.
+ * The autotuner (tune.py) measures shapes and writes the JSON file these functions
+ * read and write.  nseg = 0 lets the library choose the j-split from n.
+ * ---------------------------------------------------------------------------- */
+#define NBODY_KERNEL_FORCE 0
+#define NBODY_KERNEL_VJP 1
+#define NBODY_KERNEL_BATCHED 2
+NBODY_API nbody_status nbody_tune_set(int32_t kernel, int32_t precision, int64_t n, int32_t ipl,
+                                      int32_t jtile, int32_t nseg);
+/* shape[0..3) = ipl, jtile, nseg in effect for (kernel, precision, n). */
+NBODY_API nbody_status nbody_tune_get(int32_t kernel, int32_t precision, int64_t n,
+                                      int32_t *shape);
+NBODY_API nbody_status nbody_tune_load(const char *path);
+NBODY_API nbody_status nbody_tune_save(const char *path);
+NBODY_API void nbody_tune_reset(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -53,7 +53,7 @@ class NBodyError(RuntimeError):
         self.status = status
 
 
-_lock = threading.Lock()
+_lock = threading.RLock()
 _lib = None
 
 _I64 = ctypes.c_int64
@@ -88,7 +88,20 @@ SIGNATURES = {
     "nbody_leapfrog_batched": (_I32, [_P, _P, _P, _P, _P, _D, _I32, _P, _P, _I32, _P]),
     "nbody_graph_create_leapfrog_batched": (_I32, [_P, _P, _P, _P, _P, _D, _I32, _P, _P, _P,
                                                    ctypes.POINTER(_P)]),
+    "nbody_tune_set": (_I32, [_I32, _I32, _I64, _I32, _I32, _I32]),
+    "nbody_tune_get": (_I32, [_I32, _I32, _I64, ctypes.POINTER(_I32)]),
+    "nbody_tune_load": (_I32, [ctypes.c_char_p]),
+    "nbody_tune_save": (_I32, [ctypes.c_char_p]),
+    "nbody_tune_reset": (None, []),
 }
+
+NBODY_KERNEL_FORCE = 0
+NBODY_KERNEL_VJP = 1
+NBODY_KERNEL_BATCHED = 2
+KERNELS = {"force": NBODY_KERNEL_FORCE, "vjp": NBODY_KERNEL_VJP, "batched": NBODY_KERNEL_BATCHED}
+# Tuning table shipped with the package (measured on MI355X by tune.py); loaded with
+# the library when present.
+TUNING_PATH = os.path.join(_PKG, "tuning_gfx950.json")
 
 NBODY_LF_INIT_ACC = 1
 
@@ -108,6 +121,9 @@ def load():
                 f.restype = res
                 f.argtypes = args
             _lib = lib
+            path = os.environ.get("NBODY_TUNING_FILE", TUNING_PATH)
+            if path and os.path.exists(path):
+                _check(lib.nbody_tune_load(path.encode()), "nbody_tune_load")
     return _lib
 
 
@@ -246,3 +262,25 @@ def nbody_graph_create_leapfrog_batched(plan, pos64, vel64, mass, eps, dt, nstep
                                                     acc, pot, stream, ctypes.byref(h))
     _check(st, "nbody_graph_create_leapfrog_batched")
     return h.value
+
+
+def nbody_tune_set(kernel, precision, n, ipl, jtile, nseg):
+    return _check(load().nbody_tune_set(kernel, precision, n, ipl, jtile, nseg), "nbody_tune_set")
+
+
+def nbody_tune_get(kernel, precision, n):
+    shape = (_I32 * 3)()
+    _check(load().nbody_tune_get(kernel, precision, n, shape), "nbody_tune_get")
+    return int(shape[0]), int(shape[1]), int(shape[2])
+
+
+def nbody_tune_load(path):
+    return _check(load().nbody_tune_load(str(path).encode()), "nbody_tune_load")
+
+
+def nbody_tune_save(path):
+    return _check(load().nbody_tune_save(str(path).encode()), "nbody_tune_save")
+
+
+def nbody_tune_reset():
+    load().nbody_tune_reset()

@@ -1,9 +1,20 @@
-// Launch-shape table (see tuning.h).
+// Launch-shape table (see tuning.h) and its JSON form.
+//
+// File format (written by nbody_tune_save and by tune.py):
+//   {"version": 1, "arch": "gfx950", "entries": [
+//     {"kernel": 0, "precision": 2, "bucket": 17, "ipl": 4, "jtile": 256, "nseg": 16}, ...]}
+// kernel: 0 force, 1 adjoint, 2 batched; precision: 0 plain, 1 FP64-reduced,
+// 2 compensated; bucket: floor(log2 n) of the particle count (batched: mean system
+// size).  Unknown keys are ignored.
 #include "tuning.h"
 
+#include <cctype>
+#include <cstdio>
+#include <cstdlib>
 #include <mutex>
+#include <string>
 
-#include "nbody.h"
+#include "nbody_internal.h"
 
 namespace nbody {
 namespace {
@@ -12,12 +23,6 @@ constexpr int kBuckets = 32;
 std::mutex g_mu;
 bool g_set[KERNEL_COUNT][3][kBuckets];
 TuneEntry g_tab[KERNEL_COUNT][3][kBuckets];
-
-int bucket(int64_t n) {
-    int b = 0;
-    while (b + 1 < kBuckets && (int64_t(1) << (b + 1)) <= n) ++b;
-    return b;
-}
 
 TuneEntry builtin(int kernel, int64_t n) {
     if (kernel == KERNEL_BATCHED) {
@@ -38,12 +43,26 @@ TuneEntry builtin(int kernel, int64_t n) {
     return {1, 128, 0};
 }
 
+bool valid_entry(int kernel, int precision, int bucket, const TuneEntry &e) {
+    return kernel >= 0 && kernel < KERNEL_COUNT && precision >= 0 && precision <= 2 &&
+           bucket >= 0 && bucket < kBuckets &&
+           (e.ipl == 1 || e.ipl == 2 || e.ipl == 4 || e.ipl == 8) &&
+           (e.jt == 64 || e.jt == 128 || e.jt == 256 || e.jt == 512) && e.nseg >= 0 &&
+           e.nseg <= kMaxSeg;
+}
+
 }  // namespace
+
+int size_bucket(int64_t n) {
+    int b = 0;
+    while (b + 1 < kBuckets && (int64_t(1) << (b + 1)) <= n) ++b;
+    return b;
+}
 
 TuneEntry tuned_shape(int kernel, int precision, int64_t n) {
     if (kernel < 0 || kernel >= KERNEL_COUNT || precision < 0 || precision > 2) return builtin(0, n);
     std::lock_guard<std::mutex> lk(g_mu);
-    const int b = bucket(n);
+    const int b = size_bucket(n);
     if (g_set[kernel][precision][b]) return g_tab[kernel][precision][b];
     return builtin(kernel, n);
 }
@@ -51,9 +70,114 @@ TuneEntry tuned_shape(int kernel, int precision, int64_t n) {
 void set_tuned_shape(int kernel, int precision, int64_t n, const TuneEntry &e) {
     if (kernel < 0 || kernel >= KERNEL_COUNT || precision < 0 || precision > 2) return;
     std::lock_guard<std::mutex> lk(g_mu);
-    const int b = bucket(n);
+    const int b = size_bucket(n);
     g_tab[kernel][precision][b] = e;
     g_set[kernel][precision][b] = true;
 }
 
 }  // namespace nbody
+
+using namespace nbody;
+
+extern "C" {
+
+nbody_status nbody_tune_set(int32_t kernel, int32_t precision, int64_t n, int32_t ipl,
+                            int32_t jtile, int32_t nseg) {
+    clear_error();
+    const TuneEntry e{ipl, jtile, nseg};
+    if (n < 1 || !valid_entry(kernel, precision, size_bucket(n), e))
+        return set_error(NBODY_EINVAL, "invalid tuning entry");
+    set_tuned_shape(kernel, precision, n, e);
+    return NBODY_OK;
+}
+
+nbody_status nbody_tune_get(int32_t kernel, int32_t precision, int64_t n, int32_t *shape) {
+    clear_error();
+    if (!shape || kernel < 0 || kernel >= KERNEL_COUNT || precision < 0 || precision > 2 || n < 1)
+        return set_error(NBODY_EINVAL, "invalid tuning query");
+    const TuneEntry e = tuned_shape(kernel, precision, n);
+    shape[0] = e.ipl;
+    shape[1] = e.jt;
+    shape[2] = e.nseg;
+    return NBODY_OK;
+}
+
+void nbody_tune_reset(void) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (auto &a : g_set)
+        for (auto &b : a)
+            for (bool &c : b) c = false;
+}
+
+nbody_status nbody_tune_save(const char *path) {
+    clear_error();
+    if (!path) return set_error(NBODY_EINVAL, "path must not be NULL");
+    FILE *f = std::fopen(path, "w");
+    if (!f) return set_error(NBODY_EINVAL, std::string("cannot write ") + path);
+    std::fprintf(f, "{\"version\": 1, \"arch\": \"gfx950\", \"entries\": [");
+    bool first = true;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        for (int k = 0; k < KERNEL_COUNT; ++k)
+            for (int p = 0; p < 3; ++p)
+                for (int b = 0; b < kBuckets; ++b)
+                    if (g_set[k][p][b]) {
+                        const TuneEntry &e = g_tab[k][p][b];
+                        std::fprintf(f, "%s\n  {\"kernel\": %d, \"precision\": %d, \"bucket\": %d, "
+                                        "\"ipl\": %d, \"jtile\": %d, \"nseg\": %d}",
+                                     first ? "" : ",", k, p, b, e.ipl, e.jt, e.nseg);
+                        first = false;
+                    }
+    }
+    std::fprintf(f, "\n]}\n");
+    const bool ok = std::fclose(f) == 0;
+    return ok ? NBODY_OK : set_error(NBODY_EINVAL, std::string("error writing ") + path);
+}
+
+// Reads every {...} object inside the "entries" array; each holds integer fields.
+nbody_status nbody_tune_load(const char *path) {
+    clear_error();
+    if (!path) return set_error(NBODY_EINVAL, "path must not be NULL");
+    FILE *f = std::fopen(path, "r");
+    if (!f) return set_error(NBODY_EINVAL, std::string("cannot read ") + path);
+    std::string text;
+    char buf[4096];
+    size_t got;
+    while ((got = std::fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, got);
+    std::fclose(f);
+    const size_t ent = text.find("\"entries\"");
+    if (ent == std::string::npos) return set_error(NBODY_EINVAL, "no \"entries\" in tuning file");
+    size_t pos = text.find('[', ent);
+    const size_t end = text.find(']', pos == std::string::npos ? ent : pos);
+    if (pos == std::string::npos || end == std::string::npos)
+        return set_error(NBODY_EINVAL, "malformed tuning file");
+    int loaded = 0;
+    while (true) {
+        const size_t ob = text.find('{', pos);
+        if (ob == std::string::npos || ob > end) break;
+        const size_t cb = text.find('}', ob);
+        if (cb == std::string::npos) return set_error(NBODY_EINVAL, "malformed tuning entry");
+        int v[6] = {-1, -1, -1, -1, -1, -1};
+        const char *keys[6] = {"\"kernel\"", "\"precision\"", "\"bucket\"", "\"ipl\"", "\"jtile\"", "\"nseg\""};
+        for (int q = 0; q < 6; ++q) {
+            const size_t kp = text.find(keys[q], ob);
+            if (kp == std::string::npos || kp > cb) continue;
+            const size_t colon = text.find(':', kp);
+            if (colon == std::string::npos || colon > cb) continue;
+            v[q] = std::atoi(text.c_str() + colon + 1);
+        }
+        const TuneEntry e{v[3], v[4], v[5]};
+        if (!valid_entry(v[0], v[1], v[2], e))
+            return set_error(NBODY_EINVAL, "invalid tuning entry in " + std::string(path));
+        {
+            std::lock_guard<std::mutex> lk(g_mu);
+            g_tab[v[0]][v[1]][v[2]] = e;
+            g_set[v[0]][v[1]][v[2]] = true;
+        }
+        ++loaded;
+        pos = cb + 1;
+    }
+    return NBODY_OK;
+}
+
+}  // extern "C"

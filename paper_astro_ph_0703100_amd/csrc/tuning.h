@@ -14,6 +14,9 @@ struct TuneEntry {
     int nseg;  // j-segments, 0 = chosen from n
 };
 
+// floor(log2 n) (0 for n < 2): the size bucket of the table.
+int size_bucket(int64_t n);
+
 // Shape for a kernel, precision mode and problem size (size bucket = floor(log2 n)).
 TuneEntry tuned_shape(int kernel, int precision, int64_t n);
 

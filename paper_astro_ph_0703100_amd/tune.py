@@ -1,0 +1,215 @@
+"""Autotuner: measure launch shapes on the GPU and write the library's tuning table.
+
+For each workload it sweeps i-particles per lane (1, 2, 4, 8), j-tile (64 .. 512)
+and, for the single-system kernels, the number of j-segments; times every shape with
+HIP events on the launch stream (median of ``reps`` after a warm-up call); and admits
+a shape only if its result matches a reference computed on the same GPU with FP64
+reduction at the built-in shape (relative RMS <= 1e-6, plain FP32 <= 2e-5).  The
+fastest admitted shape is stored with ``nbody_tune_set`` and the table is written
+with ``nbody_tune_save``; the library loads ``tuning_gfx950.json`` next to itself.
+
+    python -m paper_astro_ph_0703100_amd.tune --out paper_astro_ph_0703100_amd/tuning_gfx950.json
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+
+import numpy as np
+import torch
+
+from . import _lib, api, ics
+from .metrics import rel_errors
+
+IPLS = (1, 2, 4, 8)
+JTILES = (64, 128, 256, 512)
+SEGS = (0, 4, 8, 10, 12, 16, 20, 24, 32, 40, 48, 64)
+GATE = {"comp": 1e-6, "fp64red": 1e-6, "plain": 2e-5}
+
+
+def _time(call, reps: int) -> float:
+    """Median milliseconds of ``call`` (events on the current stream)."""
+    call()
+    torch.cuda.synchronize()
+    times = []
+    s = torch.cuda.current_stream()
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(s)
+        call()
+        b.record(s)
+        b.synchronize()
+        times.append(a.elapsed_time(b))
+    return float(np.median(times))
+
+
+def _host(t):
+    return t.detach().cpu().numpy()
+
+
+def tune_force(n: int, seed: int, eps: float, precision: str, reps: int = 3, log=None):
+    """Sweep the single-system force kernel (with potential) for ``n`` particles."""
+    pos, _, mass = ics.plummer(n, seed=seed)
+    dev = "cuda:0"
+    p = torch.from_numpy(np.ascontiguousarray(pos.T.astype(np.float32))).to(dev)
+    m = torch.from_numpy(mass.astype(np.float32)).to(dev)
+    ref_a, ref_p = api.force(p, m, eps, precision="fp64red", ipl=1, jtile=64, nseg=1)
+    ref_a, ref_p = _host(ref_a).T, _host(ref_p)
+    acc = torch.empty((3, n), dtype=torch.float64, device=dev)
+    pot = torch.empty(n, dtype=torch.float64, device=dev)
+    best = None
+    rows = []
+    for ipl in IPLS:
+        for jt in JTILES:
+            jtiles = (n + jt - 1) // jt
+            for nseg in SEGS:
+                if nseg > jtiles:
+                    continue
+                opts = api.make_opts(precision=precision, ipl=ipl, jtile=jt, nseg=nseg)
+                call = lambda: _lib.nbody_force_ex(n, p.data_ptr(), m.data_ptr(), eps,
+                                                   acc.data_ptr(), pot.data_ptr(), opts,
+                                                   api.stream_ptr())
+                ms = _time(call, reps)
+                ea = rel_errors(_host(acc).T, ref_a)["rel_rms"]
+                ep = rel_errors(_host(pot), ref_p)["rel_rms"]
+                ok = ea <= GATE[precision] and ep <= GATE[precision]
+                row = {"kernel": "force", "precision": precision, "n": n, "ipl": ipl,
+                       "jtile": jt, "nseg": nseg, "ms": ms, "acc_rel_rms": ea, "ok": ok,
+                       "pairs_per_s": n * n / (ms * 1e-3)}
+                rows.append(row)
+                if log:
+                    log(row)
+                if ok and (best is None or ms < best["ms"]):
+                    best = row
+    return best, rows
+
+
+def tune_vjp(n: int, seed: int, eps: float, precision: str, reps: int = 3, log=None):
+    pos, _, mass = ics.plummer(n, seed=seed)
+    dev = "cuda:0"
+    rng = np.random.default_rng(seed + 1)
+    p = torch.from_numpy(np.ascontiguousarray(pos.T.astype(np.float32))).to(dev)
+    m = torch.from_numpy(mass.astype(np.float32)).to(dev)
+    g = torch.from_numpy(rng.standard_normal((3, n))).to(dev)
+    gx = torch.empty((3, n), dtype=torch.float64, device=dev)
+    gm = torch.empty(n, dtype=torch.float64, device=dev)
+
+    def run(opts):
+        return lambda: _lib.nbody_force_vjp(n, p.data_ptr(), m.data_ptr(), eps, g.data_ptr(),
+                                            None, gx.data_ptr(), gm.data_ptr(), opts,
+                                            api.stream_ptr())
+    run(api.make_opts(precision="fp64red", ipl=1, jtile=64, nseg=1))()
+    torch.cuda.synchronize()
+    ref = _host(gx).T.copy()
+    best, rows = None, []
+    for ipl in IPLS:
+        for jt in JTILES:
+            jtiles = (n + jt - 1) // jt
+            for nseg in SEGS:
+                if nseg > jtiles:
+                    continue
+                ms = _time(run(api.make_opts(precision=precision, ipl=ipl, jtile=jt, nseg=nseg)),
+                           reps)
+                e = rel_errors(_host(gx).T, ref)["normwise"]
+                ok = e <= 1e-6
+                row = {"kernel": "vjp", "precision": precision, "n": n, "ipl": ipl, "jtile": jt,
+                       "nseg": nseg, "ms": ms, "normwise": e, "ok": ok,
+                       "pairs_per_s": n * n / (ms * 1e-3)}
+                rows.append(row)
+                if log:
+                    log(row)
+                if ok and (best is None or ms < best["ms"]):
+                    best = row
+    return best, rows
+
+
+def tune_batched(nsys: int, seed: int, eps: float, precision: str, reps: int = 3, log=None):
+    b = ics.cluster_batch(nsys, seed=seed, eps=eps)
+    dev = "cuda:0"
+    p = torch.from_numpy(np.ascontiguousarray(b.pos.T.astype(np.float32))).to(dev)
+    m = torch.from_numpy(b.mass.astype(np.float32)).to(dev)
+    e = torch.from_numpy(b.eps.astype(np.float32)).to(dev)
+    ref_plan = api.BatchPlan(b.offsets, precision="fp64red", ipl=1, jtile=64)
+    ref_a, _ = ref_plan.force(p, m, e)
+    ref_a = _host(ref_a).T.copy()
+    ref_plan.close()
+    best, rows = None, []
+    mean_n = int(b.offsets[-1] // max(1, nsys))
+    for ipl in IPLS:
+        for jt in JTILES:
+            plan = api.BatchPlan(b.offsets, precision=precision, ipl=ipl, jtile=jt)
+            info = plan.info()
+            acc, pot = plan.force(p, m, e)
+            ms = _time(lambda: plan.force(p, m, e, with_pot=True), reps)
+            acc, _ = plan.force(p, m, e)
+            err = rel_errors(_host(acc).T, ref_a)["rel_rms"]
+            ok = err <= GATE[precision]
+            row = {"kernel": "batched", "precision": precision, "n": mean_n, "nsys": nsys,
+                   "ipl": ipl, "jtile": jt, "nseg": 0, "ms": ms, "acc_rel_rms": err, "ok": ok,
+                   "pairs_per_s": info["pairs"] / (ms * 1e-3), "items": info["items"],
+                   "padded_pairs": info["padded_pairs"]}
+            rows.append(row)
+            if log:
+                log(row)
+            if ok and (best is None or ms < best["ms"]):
+                best = row
+            plan.close()
+    return best, rows
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--out", default=_lib.TUNING_PATH)
+    ap.add_argument("--report", default="", help="write every measured shape here (JSON lines)")
+    ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--quick", action="store_true", help="force kernel at N=131072 only")
+    args = ap.parse_args(argv)
+
+    _lib.load()
+    _lib.nbody_tune_reset()  # measure against the built-in shapes, not an old table
+    rep = open(args.report, "w") if args.report else None
+
+    def log(row):
+        if rep:
+            rep.write(json.dumps(row) + "\n")
+            rep.flush()
+
+    jobs = []
+    w = ics.WORKLOADS["plummer_131072"]
+    eps = float(np.float32(w.eps))
+    for prec in ("comp", "plain", "fp64red"):
+        jobs.append(("force", prec, lambda prec=prec: tune_force(w.n, w.seed, eps, prec, args.reps, log)))
+    if not args.quick:
+        for n in (2048, 16384, 32768):
+            jobs.append(("force", "comp", lambda n=n: tune_force(n, 10 + n, 0.01, "comp", args.reps, log)))
+        wa = ics.WORKLOADS["adjoint_16384"]
+        jobs.append(("vjp", "comp", lambda: tune_vjp(wa.n, wa.seed, float(np.float32(wa.eps)), "comp",
+                                                     args.reps, log)))
+        wb = ics.WORKLOADS["clusters_2048"]
+        jobs.append(("batched", "comp", lambda: tune_batched(wb.n, wb.seed, wb.eps, "comp",
+                                                             args.reps, log)))
+    summary = []
+    for kernel, prec, job in jobs:
+        best, rows = job()
+        if best is None:
+            print("tune: no shape passed the parity gate for %s/%s" % (kernel, prec), file=sys.stderr)
+            continue
+        _lib.nbody_tune_set(_lib.KERNELS[kernel], _lib.PRECISIONS[prec], best["n"], best["ipl"],
+                            best["jtile"], best["nseg"])
+        default = [r for r in rows if r["ok"]]
+        print("tune: %-7s %-7s n=%-7d best ipl=%d jtile=%d nseg=%d  %.3f ms  %.3g pairs/s "
+              "(%d shapes, slowest admitted %.3f ms)"
+              % (kernel, prec, best["n"], best["ipl"], best["jtile"], best["nseg"], best["ms"],
+                 best["pairs_per_s"], len(rows), max(r["ms"] for r in default)), flush=True)
+        summary.append(best)
+    _lib.nbody_tune_save(args.out)
+    print("tune: wrote %s" % args.out, flush=True)
+    if rep:
+        rep.close()
+    return summary
+
+
+if __name__ == "__main__":
+    main()

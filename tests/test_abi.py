@@ -163,3 +163,43 @@ def test_vjp_and_adjoint_reject_invalid_arguments():
     assert adj(10, FAKE, FAKE, 0.1, float("nan"), 2, FAKE, FAKE, None, o, None, check=False) == _lib.NBODY_EINVAL
     assert adj(10, FAKE, FAKE, 0.1, 0.01, 2, FAKE, None, None, o, None, check=False) == _lib.NBODY_EINVAL
     assert adj(0, None, None, 0.1, 0.01, 2, None, None, None, o, None, check=False) == _lib.NBODY_OK
+
+
+def test_tuning_table_roundtrip(tmp_path):
+    _lib.nbody_tune_reset()
+    base = _lib.nbody_tune_get(_lib.NBODY_KERNEL_FORCE, _lib.NBODY_COMP, 131072)
+    assert base[0] in (1, 2, 4, 8) and base[1] in (64, 128, 256, 512)
+    _lib.nbody_tune_set(_lib.NBODY_KERNEL_FORCE, _lib.NBODY_COMP, 131072, 8, 512, 12)
+    _lib.nbody_tune_set(_lib.NBODY_KERNEL_VJP, _lib.NBODY_PLAIN, 5000, 1, 64, 3)
+    assert _lib.nbody_tune_get(_lib.NBODY_KERNEL_FORCE, _lib.NBODY_COMP, 131072) == (8, 512, 12)
+    # Same size bucket (floor(log2 n) = 17), other precision untouched.
+    assert _lib.nbody_tune_get(_lib.NBODY_KERNEL_FORCE, _lib.NBODY_COMP, 200000) == (8, 512, 12)
+    assert _lib.nbody_tune_get(_lib.NBODY_KERNEL_FORCE, _lib.NBODY_PLAIN, 131072) == base
+    path = tmp_path / "t.json"
+    _lib.nbody_tune_save(path)
+    _lib.nbody_tune_reset()
+    assert _lib.nbody_tune_get(_lib.NBODY_KERNEL_FORCE, _lib.NBODY_COMP, 131072) == base
+    _lib.nbody_tune_load(path)
+    assert _lib.nbody_tune_get(_lib.NBODY_KERNEL_FORCE, _lib.NBODY_COMP, 131072) == (8, 512, 12)
+    assert _lib.nbody_tune_get(_lib.NBODY_KERNEL_VJP, _lib.NBODY_PLAIN, 4096) == (1, 64, 3)
+    _lib.nbody_tune_reset()
+    # Workspace sizing follows the table.
+    o = _lib.nbody_opts_default()
+    w0 = _lib.nbody_workspace_size(131072, o)
+    _lib.nbody_tune_set(_lib.NBODY_KERNEL_FORCE, _lib.NBODY_COMP, 131072, 4, 256, 32)
+    assert _lib.nbody_workspace_size(131072, o) > w0
+    _lib.nbody_tune_reset()
+    if os.path.exists(_lib.TUNING_PATH):
+        _lib.nbody_tune_load(_lib.TUNING_PATH)
+
+
+def test_tuning_rejects_bad_entries(tmp_path):
+    assert _lib.load().nbody_tune_set(0, 2, 1000, 3, 256, 0) == _lib.NBODY_EINVAL
+    assert _lib.load().nbody_tune_set(0, 2, 1000, 4, 100, 0) == _lib.NBODY_EINVAL
+    assert _lib.load().nbody_tune_set(5, 2, 1000, 4, 256, 0) == _lib.NBODY_EINVAL
+    assert _lib.load().nbody_tune_set(0, 2, 0, 4, 256, 0) == _lib.NBODY_EINVAL
+    bad = tmp_path / "bad.json"
+    bad.write_text('{"entries": [{"kernel": 0, "precision": 2, "bucket": 17, "ipl": 3, '
+                   '"jtile": 256, "nseg": 0}]}')
+    assert _lib.load().nbody_tune_load(str(bad).encode()) == _lib.NBODY_EINVAL
+    assert _lib.load().nbody_tune_load(str(tmp_path / "missing.json").encode()) == _lib.NBODY_EINVAL
