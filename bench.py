@@ -64,6 +64,9 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="i-particles the oracle evaluates (0 = all N)")
     ap.add_argument("--modes", default="comp,plain,fp64red")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="run one device-to-device copy of this many MiB first (a plain copy "
+                         "kernel of known size, to calibrate hardware byte counters)")
     return ap.parse_args()
 
 
@@ -142,6 +145,14 @@ def main():
         acc, pot = api.force_f64(x0, m, eps, precision=precision)
         torch.cuda.synchronize()
         return acc.cpu().numpy().T.copy(), pot.cpu().numpy().copy()
+
+    if args.calib_copy_mb > 0:
+        nb = args.calib_copy_mb * (1 << 20) // 4
+        src = torch.ones(nb, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     res = {}
     for precision in modes:

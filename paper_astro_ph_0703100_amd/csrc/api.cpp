@@ -128,10 +128,10 @@ nbody_status choose_cfg(int kernel, int64_t n, int precision, const nbody_opts &
     const int64_t jtiles = (n + c.jt - 1) / c.jt;
     int64_t nseg = o.nseg ? o.nseg : t.nseg;
     if (nseg <= 0) {
-        const int64_t target = (int64_t)device_info().cus * 8;
+        // About 48 blocks per compute unit: enough to keep 8 waves per SIMD busy and to
+        // make the last round of blocks short (measured best at 40-64 per CU).
+        const int64_t target = (int64_t)device_info().cus * 48;
         nseg = (target + c.itiles - 1) / c.itiles;
-        const int64_t cap = jtiles / 4 > 1 ? jtiles / 4 : 1;  // at least 4 tiles per segment
-        if (nseg > cap) nseg = cap;
     }
     if (nseg > jtiles) nseg = jtiles > 0 ? jtiles : 1;
     if (nseg > kMaxSeg) nseg = kMaxSeg;

@@ -25,22 +25,12 @@ bool g_set[KERNEL_COUNT][3][kBuckets];
 TuneEntry g_tab[KERNEL_COUNT][3][kBuckets];
 
 TuneEntry builtin(int kernel, int64_t n) {
-    if (kernel == KERNEL_BATCHED) {
-        // n is the mean system size; small systems waste lanes of wide i-tiles.
-        if (n >= 2048) return {2, 128, 0};
-        return {1, 128, 0};
-    }
-    if (kernel == KERNEL_VJP) {
-        // The adjoint keeps 8 i-values and 4 accumulators (x3 when blocked) per
-        // i-particle; two per lane keep it within about 100 VGPRs.
-        if (n >= 8192) return {2, 128, 0};
-        return {1, 128, 0};
-    }
-    // More i-particles per lane amortise each LDS read over more pair terms, but
-    // leave fewer i-tiles to spread over the compute units for small n.
-    if (n >= 32768) return {4, 256, 0};
-    if (n >= 8192) return {2, 256, 0};
-    return {1, 128, 0};
+    // Measured on MI355X (tune.py): one i-particle per lane (37 VGPRs, 8 waves per
+    // SIMD) and many j-segments beat wider i-tiles for every kernel and size tried;
+    // the j-split itself is chosen from n (nseg = 0).
+    (void)n;
+    if (kernel == KERNEL_BATCHED) return {1, 64, 0};
+    return {1, 256, 0};
 }
 
 bool valid_entry(int kernel, int precision, int bucket, const TuneEntry &e) {
