@@ -65,8 +65,12 @@ typedef int32_t nbody_status;
 #define NBODY_CENTRE_NONE 0   /* pair arithmetic on fp32(x)                              */
 #define NBODY_CENTRE_SYSTEM 1 /* on fp32(x - c), c = FP64 mean position of the system;
                                  default                                                 */
-#define NBODY_CENTRE_TILE 2   /* on fp32(x - c_I), c_I = FP64 mean of the i-tile, j's
-                                 converted for each i-tile as they are staged            */
+#define NBODY_CENTRE_TILE 2   /* on fp32(x - c_I), c_I = FP64 mean of the i-tile (256 x
+                                 ipl consecutive particles), j's converted for each i-tile
+                                 as they are staged; pays off when consecutive particles
+                                 are spatially close (see nbody_morton_order).  Force and
+                                 leapfrog only (the adjoint and batched plans return
+                                 NBODY_EUNSUPPORTED).                                    */
 
 typedef struct nbody_opts {
     int32_t precision;  /* NBODY_PLAIN, NBODY_FP64RED or NBODY_COMP                   */
@@ -117,6 +121,14 @@ NBODY_API nbody_status nbody_force_ex(int64_t n, const float *pos, const float *
  * and for systems far from the origin. */
 NBODY_API nbody_status nbody_force_f64(int64_t n, const double *pos64, const float *mass, float eps,
                              double *acc, double *pot, const nbody_opts *opts, void *stream);
+
+/* Morton (Z-order) permutation of FP64 positions pos64 double [3][n]: perm int32 [n]
+ * (device, written) lists the particle indices in order along the Z-curve of the
+ * FP64 bounding box (ties broken by index).  Gathering the particles in this order
+ * makes i-tiles spatially compact, which is what NBODY_CENTRE_TILE needs.  Uses the
+ * library workspace (allocates outside capture). */
+NBODY_API nbody_status nbody_morton_order(int64_t n, const double *pos64, int32_t *perm,
+                                          void *stream);
 
 /* ------------------------------------------------------------------------------
  * Kick-drift-kick leapfrog on FP64 state (the paper has no integrator; this is the

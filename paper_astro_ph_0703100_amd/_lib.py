@@ -88,6 +88,7 @@ SIGNATURES = {
     "nbody_leapfrog_batched": (_I32, [_P, _P, _P, _P, _P, _D, _I32, _P, _P, _I32, _P]),
     "nbody_graph_create_leapfrog_batched": (_I32, [_P, _P, _P, _P, _P, _D, _I32, _P, _P, _P,
                                                    ctypes.POINTER(_P)]),
+    "nbody_morton_order": (_I32, [_I64, _P, _P, _P]),
     "nbody_tune_set": (_I32, [_I32, _I32, _I64, _I32, _I32, _I32]),
     "nbody_tune_get": (_I32, [_I32, _I32, _I64, ctypes.POINTER(_I32)]),
     "nbody_tune_load": (_I32, [ctypes.c_char_p]),
@@ -284,3 +285,8 @@ def nbody_tune_save(path):
 
 def nbody_tune_reset():
     load().nbody_tune_reset()
+
+
+def nbody_morton_order(n, pos64, perm, stream, check=True):
+    st = load().nbody_morton_order(n, pos64, perm, stream)
+    return _check(st, "nbody_morton_order") if check else st

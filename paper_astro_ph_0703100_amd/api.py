@@ -11,8 +11,8 @@ import torch
 
 from . import _lib
 
-__all__ = ["make_opts", "force", "force_f64", "leapfrog", "LeapfrogGraph", "BatchPlan", "soa",
-           "aos", "stream_ptr"]
+__all__ = ["make_opts", "force", "force_f64", "leapfrog", "LeapfrogGraph", "BatchPlan",
+           "morton_order", "soa", "aos", "stream_ptr"]
 
 
 def make_opts(precision: str = "comp", centre: str = "system", self_pot: bool = False,
@@ -82,6 +82,14 @@ def force_f64(pos64: torch.Tensor, mass: torch.Tensor, eps: float, precision: st
     _lib.nbody_force_f64(n, pos64.data_ptr(), mass.data_ptr(), float(eps), acc.data_ptr(),
                          pot.data_ptr() if pot is not None else None, opts, stream_ptr())
     return acc, pot
+
+
+def morton_order(pos64: torch.Tensor) -> torch.Tensor:
+    """int32 permutation ``[n]`` ordering the particles along the Z-curve."""
+    n = _check_pos(pos64, torch.float64, "pos64")
+    perm = torch.empty(n, dtype=torch.int32, device=pos64.device)
+    _lib.nbody_morton_order(n, pos64.data_ptr(), perm.data_ptr(), stream_ptr())
+    return perm
 
 
 def leapfrog(pos64: torch.Tensor, vel64: torch.Tensor, mass: torch.Tensor, eps: float, dt: float,

@@ -18,7 +18,7 @@ nbody_status check_vjp(int64_t n, const void *pos, const float *mass, float eps,
         misaligned(grad_mass))
         return set_error(NBODY_EINVAL, "misaligned array argument");
     if (o.centre == NBODY_CENTRE_TILE)
-        return set_error(NBODY_EUNSUPPORTED, "NBODY_CENTRE_TILE is not available");
+        return set_error(NBODY_EUNSUPPORTED, "the adjoint supports NBODY_CENTRE_NONE and _SYSTEM");
     return NBODY_OK;
 }
 
@@ -113,7 +113,7 @@ nbody_status nbody_leapfrog_adjoint(int64_t n, const double *traj, const float *
         misaligned(mbar))
         return set_error(NBODY_EINVAL, "misaligned array argument");
     if (o.centre == NBODY_CENTRE_TILE)
-        return set_error(NBODY_EUNSUPPORTED, "NBODY_CENTRE_TILE is not available");
+        return set_error(NBODY_EUNSUPPORTED, "the adjoint supports NBODY_CENTRE_NONE and _SYSTEM");
     if (n == 0) return NBODY_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
     TileCfg cfg;

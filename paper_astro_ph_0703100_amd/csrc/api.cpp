@@ -209,6 +209,20 @@ nbody_status force_f64_core(int64_t n, const double *pos64, const float *mass, f
                             double *acc, double *pot, const nbody_opts &o, const TileCfg &cfg,
                             const F64Scratch &ws, double *kick_v, double kick_h, hipStream_t s) {
     nbody_status st;
+    if (o.centre == NBODY_CENTRE_TILE) {
+        // Per-i-tile centres (3 doubles per tile fit in the FP32-position area, which this
+        // mode does not use); positions are converted inside the pair kernel.
+        const int itile = kTPB * cfg.ipl;
+        double *centres = reinterpret_cast<double *>(ws.x32);
+        if ((st = launch_tile_centres(n, itile, pos64, centres, s))) return st;
+        const float e2 = eps * eps;
+        TilePairArgs ta{pos64, pos64 + n, pos64 + 2 * n, mass, (int)n, cfg.seg_len, e2,
+                        ws.part, cfg.npad, centres, itile};
+        if ((st = launch_pair_tile(cfg, o.precision, pot != nullptr, ta, s))) return st;
+        FinalizeArgs fa{ws.part, cfg.nseg, cfg.npad, (int)n, mass, e2, o.self_pot ? 0 : 1,
+                        acc,     pot,      kick_v,   kick_h};
+        return launch_finalize(o.precision, fa, s);
+    }
     if (o.centre == NBODY_CENTRE_SYSTEM) {
         if ((st = launch_centre(n, pos64, ws.centre, ws.centre_scratch, s))) return st;
         if ((st = launch_convert(n, pos64, ws.centre, ws.x32, s))) return st;
@@ -278,8 +292,6 @@ nbody_status nbody_force_f64(int64_t n, const double *pos64, const float *mass, 
     if (st) return st;
     if (misaligned(pos64) || misaligned(mass) || misaligned(acc) || misaligned(pot))
         return set_error(NBODY_EINVAL, "misaligned array argument");
-    if (o.centre == NBODY_CENTRE_TILE)
-        return set_error(NBODY_EUNSUPPORTED, "NBODY_CENTRE_TILE is not available");
     if (n == 0) return NBODY_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
     TileCfg cfg;
@@ -288,6 +300,20 @@ nbody_status nbody_force_f64(int64_t n, const double *pos64, const float *mass, 
     if ((st = get_workspace(o, f64_scratch_bytes(n, cfg, o.precision), s, &ws))) return st;
     return force_f64_core(n, pos64, mass, eps, acc, pot, o, cfg,
                           f64_scratch_layout(ws, n, cfg, o.precision), nullptr, 0.0, s);
+}
+
+nbody_status nbody_morton_order(int64_t n, const double *pos64, int32_t *perm, void *stream) {
+    clear_error();
+    if (n < 0 || n > INT32_MAX / 2) return set_error(NBODY_EINVAL, "n must be in [0, 2^30)");
+    if (n > 0 && (!pos64 || !perm)) return set_error(NBODY_EINVAL, "pos64 and perm must not be NULL");
+    if (misaligned(pos64) || misaligned(perm)) return set_error(NBODY_EINVAL, "misaligned array argument");
+    if (n == 0) return NBODY_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    nbody_opts o = resolve_opts(nullptr);
+    void *ws = nullptr;
+    nbody_status st = get_workspace(o, morton_scratch_bytes(n), s, &ws);
+    if (st) return st;
+    return launch_morton_order(n, pos64, perm, ws, s);
 }
 
 }  // extern "C"

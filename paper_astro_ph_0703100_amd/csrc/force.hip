@@ -79,7 +79,50 @@ __global__ __launch_bounds__(256) void convert_kernel(int64_t n, const double *p
     for (int c = 0; c < 3; ++c) out[c * n + i] = (float)(pos[c * n + i] - (centre ? centre[c] : 0.0));
 }
 
+// Mean position of each i-tile of `itile` consecutive particles, FP64, one block per
+// tile, fixed-order tree: the reference centres of NBODY_CENTRE_TILE.
+__global__ __launch_bounds__(256) void tile_centre_kernel(int64_t n, int itile, const double *pos,
+                                                         double *centres) {
+    __shared__ double sh[3][256];
+    const int64_t b = (int64_t)blockIdx.x * itile;
+    const int64_t e = b + itile < n ? b + itile : n;
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int64_t p = b + threadIdx.x; p < e; p += 256)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) s[c] += pos[c * n + p];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) sh[c][threadIdx.x] = s[c];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) sh[c][threadIdx.x] += sh[c][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) centres[3 * blockIdx.x + threadIdx.x] = sh[threadIdx.x][0] / (double)(e - b);
+}
+
 }  // namespace
+
+nbody_status launch_tile_centres(int64_t n, int itile, const double *pos64, double *centres,
+                                 hipStream_t s) {
+    if (n <= 0) return NBODY_OK;
+    const int64_t tiles = (n + itile - 1) / itile;
+    hipLaunchKernelGGL(tile_centre_kernel, dim3((unsigned)tiles), dim3(256), 0, s, n, itile, pos64,
+                       centres);
+    NBODY_HIP_CHECK(hipGetLastError());
+    return NBODY_OK;
+}
+
+nbody_status launch_pair_tile(const TileCfg &cfg, int precision, bool with_pot,
+                              const TilePairArgs &a, hipStream_t s) {
+    auto fn = engine::pick_tile<GravityTile>(cfg.ipl, cfg.jt, precision, with_pot);
+    if (!fn) return set_error(NBODY_EUNSUPPORTED, "no tile-centre kernel for this shape");
+    if (cfg.itiles <= 0 || cfg.nseg <= 0) return NBODY_OK;
+    hipLaunchKernelGGL(fn, dim3(cfg.itiles, cfg.nseg), dim3(kTPB), 0, s, a);
+    NBODY_HIP_CHECK(hipGetLastError());
+    return NBODY_OK;
+}
 
 nbody_status launch_pair(const TileCfg &cfg, int precision, bool with_pot, const PairArgs &a,
                          hipStream_t s) {

@@ -14,10 +14,12 @@ struct Gravity {
     struct IState {
         float x, y, z;
     };
-    static __device__ __forceinline__ IState load_i(const Args &a, int i) {
+    struct Ctx {};
+    static __device__ __forceinline__ Ctx make_ctx(const Args &, int) { return {}; }
+    static __device__ __forceinline__ IState load_i(const Args &a, const Ctx &, int i) {
         return {a.x[i], a.y[i], a.z[i]};
     }
-    static __device__ __forceinline__ void load_j(const Args &a, int j, float (&r)[4]) {
+    static __device__ __forceinline__ void load_j(const Args &a, const Ctx &, int j, float (&r)[4]) {
         r[0] = a.x[j];
         r[1] = a.y[j];
         r[2] = a.z[j];
@@ -48,6 +50,41 @@ struct Gravity {
         acc[1] = __builtin_fmaf(mri3, dy, acc[1]);
         acc[2] = __builtin_fmaf(mri3, dz, acc[2]);
         if (POT) acc[3] = acc[3] - mri;
+    }
+};
+
+// The same pair body on FP64 positions taken relative to a per-i-tile FP64 reference
+// centre c_I (the mean of the tile's positions): the i-records and every j-record
+// staged for the tile are converted as fp32(x - c_I) while they are loaded, so the
+// FP32 pair arithmetic sees coordinates of the size of the tile, not of the system.
+// For the j == i pair both conversions are the same operation, so the separation is
+// still exactly zero.
+struct GravityTile {
+    static constexpr int kJWords = 4;
+    static constexpr int kOut = 4;
+    using Args = TilePairArgs;
+    using IState = Gravity::IState;
+    struct Ctx {
+        double cx, cy, cz;
+    };
+    static __device__ __forceinline__ Ctx make_ctx(const Args &a, int i0) {
+        const double *c = a.centres + 3 * (size_t)(i0 / a.itile);
+        return {c[0], c[1], c[2]};
+    }
+    static __device__ __forceinline__ IState load_i(const Args &a, const Ctx &c, int i) {
+        return {(float)(a.x[i] - c.cx), (float)(a.y[i] - c.cy), (float)(a.z[i] - c.cz)};
+    }
+    static __device__ __forceinline__ void load_j(const Args &a, const Ctx &c, int j, float (&r)[4]) {
+        r[0] = (float)(a.x[j] - c.cx);
+        r[1] = (float)(a.y[j] - c.cy);
+        r[2] = (float)(a.z[j] - c.cz);
+        r[3] = a.m[j];
+    }
+    static __device__ __forceinline__ void pad_j(float (&r)[4]) { Gravity::pad_j(r); }
+    template <bool POT>
+    static __device__ __forceinline__ void pair(const float *j, const IState &i, float eps2,
+                                                float (&acc)[4]) {
+        Gravity::pair<POT>(j, i, eps2, acc);
     }
 };
 

@@ -25,8 +25,6 @@ nbody_status check_leapfrog(int64_t n, const double *x, const double *v, const f
         return set_error(NBODY_EINVAL, "dt must be finite");
     if (misaligned(x) || misaligned(v) || misaligned(m) || misaligned(acc))
         return set_error(NBODY_EINVAL, "misaligned array argument");
-    if (o.centre == NBODY_CENTRE_TILE)
-        return set_error(NBODY_EUNSUPPORTED, "NBODY_CENTRE_TILE is not available");
     return NBODY_OK;
 }
 

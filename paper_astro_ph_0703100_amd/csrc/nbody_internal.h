@@ -53,6 +53,19 @@ struct PairArgs {
     int npad;
 };
 
+// Arguments of the pair kernel on FP64 positions with per-i-tile reference centres.
+struct TilePairArgs {
+    const double *x, *y, *z;  // FP64 positions [3][n]
+    const float *m;
+    int n;
+    int seg_len;
+    float eps2;
+    void *part;
+    int npad;
+    const double *centres;  // [i-tiles][3] FP64 centres
+    int itile;              // particles per i-tile (256 * IPL)
+};
+
 // One work item of a ragged batch: an i-tile of one system against a j-range of the
 // same system.  Indices are global (into the concatenated arrays).
 struct BatchItem {
@@ -192,6 +205,16 @@ nbody_status launch_convert(int64_t n, const double *pos64, const double *centre
                             hipStream_t s);
 // Bytes of the centre-reduction scratch (partials of the two-stage FP64 sum).
 size_t centre_scratch_bytes();
+// Per-i-tile FP64 centres (mean position of each tile of `itile` particles) and the pair
+// kernel that converts positions relative to them (force.hip).
+nbody_status launch_tile_centres(int64_t n, int itile, const double *pos64, double *centres,
+                                 hipStream_t s);
+nbody_status launch_pair_tile(const TileCfg &cfg, int precision, bool with_pot,
+                              const TilePairArgs &a, hipStream_t s);
+// Morton (Z-order) permutation of FP64 positions (morton.hip).
+nbody_status launch_morton_order(int64_t n, const double *pos64, int32_t *perm, void *scratch,
+                                 hipStream_t s);
+size_t morton_scratch_bytes(int64_t n);
 // Leapfrog pieces (leapfrog.hip).
 nbody_status launch_kick_drift(int64_t n, double *x, double *v, const double *acc, double h,
                                double dt, hipStream_t s);

@@ -29,8 +29,10 @@
 //   static constexpr int kOut;               // outputs per i (<= 4)
 //   struct Args;                             // kernel arguments (n, seg_len, eps2, part, npad, ...)
 //   struct IState;                           // per-i registers
-//   static IState load_i(const Args&, int i);
-//   static void load_j(const Args&, int j, float (&r)[kJWords]);
+//   struct Ctx;                              // per-block context (e.g. a reference centre)
+//   static Ctx make_ctx(const Args&, int i0);
+//   static IState load_i(const Args&, const Ctx&, int i);
+//   static void load_j(const Args&, const Ctx&, int j, float (&r)[kJWords]);
 //   static void pad_j(float (&r)[kJWords]);  // a record that adds exactly zero
 //   template <bool FULL> static void pair(const float *jr, const IState&, float eps2,
 //                                         float (&acc)[kOut]);
@@ -118,12 +120,13 @@ __device__ __forceinline__ void block_work(const typename Op::Args &a, float4 (*
     constexpr int LPT = (JT + kTPB - 1) / kTPB;  // j-records staged per lane
     static_assert(W % 4 == 0, "j-records are whole float4s");
     const int tid = threadIdx.x;
+    const typename Op::Ctx ctx = Op::make_ctx(a, i0);
 
     typename Op::IState is[IPL];
 #pragma unroll
     for (int k = 0; k < IPL; ++k) {
         const int r = k * kTPB + tid;
-        is[k] = Op::load_i(a, i0 + (r < ni ? r : ni - 1));
+        is[k] = Op::load_i(a, ctx, i0 + (r < ni ? r : ni - 1));
     }
 
     float hs[IPL][NO], ls[IPL][NO];
@@ -148,7 +151,7 @@ __device__ __forceinline__ void block_work(const typename Op::Args &a, float4 (*
             const int j = j0 + t * JT + jj;
             if (jj < JT) {
                 if (j < j1)
-                    Op::load_j(a, j, stage[q]);
+                    Op::load_j(a, ctx, j, stage[q]);
                 else
                     Op::pad_j(stage[q]);
             }

@@ -26,11 +26,13 @@ struct Adjoint {
     struct IState {
         float x, y, z, m, gx, gy, gz, p;
     };
-    static __device__ __forceinline__ IState load_i(const Args &a, int i) {
+    struct Ctx {};
+    static __device__ __forceinline__ Ctx make_ctx(const Args &, int) { return {}; }
+    static __device__ __forceinline__ IState load_i(const Args &a, const Ctx &, int i) {
         return {a.x[i], a.y[i], a.z[i], a.m[i], (float)a.gx[i], (float)a.gy[i], (float)a.gz[i],
                 a.gp ? (float)a.gp[i] : 0.0f};
     }
-    static __device__ __forceinline__ void load_j(const Args &a, int j, float (&r)[8]) {
+    static __device__ __forceinline__ void load_j(const Args &a, const Ctx &, int j, float (&r)[8]) {
         r[0] = a.x[j];
         r[1] = a.y[j];
         r[2] = a.z[j];
