@@ -1,31 +1,44 @@
 #!/usr/bin/env python3
 """Throughput of the direct-sum gravity path on one MI355X, with accuracy and roofline.
 
-Workload (default ``plummer_131072``): N = 131072 equal-mass Plummer sphere (scale 1,
+Default workload ``plummer_131072``: N = 131072 equal-mass Plummer sphere (scale 1,
 total mass 1, truncated at 20 scale radii, distribution-function velocities), seed 2,
-eps = 0.4 / N^{1/3}, FP32 masses, FP64 positions and velocities.
+eps = 0.4 / N^{1/3}, FP32 masses, FP64 positions and velocities.  A step is one
+kick-drift-kick leapfrog step (dt = 1/256) replayed from a HIP graph: first kick +
+drift (FP64), FP64 centre, FP32 conversion, pair kernel (N^2 pair interactions:
+accelerations and potentials, compensated FP32 accumulation), FP64 reduction fused
+with the second kick.  ``value`` is N^2 * steps / wall time (pair interactions per
+second, inputs resident in HBM).  The same is timed with plain FP32 accumulation and
+with FP64-reduced accumulation ("modes").
 
-A step is one kick-drift-kick leapfrog step (dt = 1/256) replayed from a HIP graph:
-first kick + drift (FP64), FP64 centre, FP32 conversion, pair kernel (N^2 pair
-interactions: accelerations and potentials, compensated FP32 accumulation), FP64
-reduction fused with the second kick.  ``value`` is N^2 * steps / wall time (pair interactions per second, inputs
-resident in HBM).  The same is timed with plain FP32 accumulation.
+Other workloads (same JSON shape; ``value`` always counts the pair interactions the
+step evaluates):
+  stress_1m      2^20-particle precision-stress system at (1000,0,0), Morton-ordered,
+                 per-i-tile FP64 centres; step = one force+potential evaluation.
+  clusters_2048  2048 ragged Plummer clusters; step = one graph-replayed batched KDK
+                 step (persistent work-queue kernel); pairs = sum N_k^2.
+  adjoint_16384  N = 16384, 32 KDK steps dt = 1/256 and the reverse pass; step = one
+                 loss + gradient (33 force and 33 adjoint evaluations of N^2 pairs).
 
-Roofline: the pair kernel (plus its FP64 finalize) is timed with HIP events around
-standalone force evaluations on the same stream, and compared with the issue limit
-of 17 VALU slots per pair.
+Roofline: the dominant kernel's duration is taken from HIP events on the launch
+stream (standalone calls), and compared with the VALU issue limit:
+17 slots per gravity pair, 42 per adjoint pair, at 256 CUs x 4 SIMDs x 32 lanes x
+2.4 GHz.  ``traffic`` comes from the committed rocprofv3 counter summary of the
+same kernel and is null when the kernel sources changed since it was taken.
 
-Accuracy: the CPU-baseline leg runs the FP64 oracle on the initial positions (all N
-i-particles by default); its result gives the relative RMS and maximum (eq. (3))
-errors of each mode's force evaluation, and its wall time the CPU rate.
+Accuracy: the CPU-baseline leg runs the FP64 oracle on a bounded sample of the same
+workload; its result gives the relative RMS and maximum (eq. (3)) errors of each
+mode, and its wall time the CPU rate.
 
 Prints one JSON line.  ``--gpus`` above 1 is refused: the path runs on one GPU.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -41,16 +54,43 @@ METRIC = "pair interactions/s at N=131072, compensated vs plain FP32, error vs F
 # clock (a wave64 FP32 add/mul/FMA every 2 clocks, which is the 157.3 TFLOP/s FP32
 # figure with FMA = 2 flops) at 2.4 GHz: 7.86e13 lane-operations per second.  A
 # transcendental (v_rsq_f32) issues at a quarter of that rate, so it takes 4 slots.
-# A pair term needs 13 FP32 VALU operations plus one v_rsq_f32: 17 slots.
 CUS, SIMDS, LANES, CLOCK_HZ = 256, 4, 32, 2.4e9
 LANE_ISSUE = CUS * SIMDS * LANES * CLOCK_HZ
-VALU_PER_PAIR = 13
-RSQ_SLOTS = 4.0
-FLOPS_PER_PAIR = 20  # the paper's operation count per pair (Sec. 1.1)
+RSQ_SLOTS = 4
+SLOTS = {"gravity": 13 + RSQ_SLOTS, "adjoint": 38 + RSQ_SLOTS}
+FLOPS = {"gravity": 20, "adjoint": 45}  # the paper's count per gravity pair (Sec. 1.1)
+
+# Kernel sources behind the committed counter summaries (traffic is dropped when they change).
+KERNEL_SOURCES = ["paper_astro_ph_0703100_amd/csrc/tile_engine.h",
+                  "paper_astro_ph_0703100_amd/csrc/gravity.h",
+                  "paper_astro_ph_0703100_amd/csrc/force.hip",
+                  "paper_astro_ph_0703100_amd/tuning_gfx950.json"]
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "pair_kernel_plummer_131072.md")
 
 
-def peak_pairs_per_s() -> float:
-    return LANE_ISSUE / (VALU_PER_PAIR + RSQ_SLOTS)
+def peak_pairs(kind: str) -> float:
+    return LANE_ISSUE / SLOTS[kind]
+
+
+def sources_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def committed_traffic():
+    """HBM bytes per launch of the pair kernel from the committed counter summary, or None."""
+    try:
+        text = open(TRAFFIC_SUMMARY).read()
+    except OSError:
+        return None
+    m = re.search(r"<!-- traffic: (\{.*?\}) -->", text)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    return rec["bytes_per_launch"] if rec.get("sources_hash") == sources_hash() else None
 
 
 def parse():
@@ -58,16 +98,349 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=8)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="plummer_131072")
+    ap.add_argument("--workload", default="plummer_131072",
+                    choices=["plummer_131072", "plummer_2048", "stress_1m", "clusters_2048",
+                             "adjoint_16384"])
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the FP64 oracle leg (no errors, no CPU rate)")
     ap.add_argument("--cpu-sample", type=int, default=0,
-                    help="i-particles the oracle evaluates (0 = all N)")
+                    help="i-particles the oracle evaluates (0 = the workload's default)")
     ap.add_argument("--modes", default="comp,plain,fp64red")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
-                    help="run one device-to-device copy of this many MiB first (a plain copy "
-                         "kernel of known size, to calibrate hardware byte counters)")
+                    help="first run one device-to-device copy of this many MiB from a source "
+                         "evicted from the caches (a plain copy kernel of known size, to "
+                         "calibrate hardware byte counters)")
     return ap.parse_args()
+
+
+class Timer:
+    """HIP events around calls on the current stream."""
+
+    def __init__(self, torch):
+        self.torch = torch
+        self.stream = torch.cuda.current_stream()
+
+    def run(self, call, reps, warmup=1):
+        torch = self.torch
+        for _ in range(warmup):
+            call()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(reps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for a, b in ev:
+            a.record(self.stream)
+            call()
+            b.record(self.stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        return wall, [a.elapsed_time(b) for a, b in ev]
+
+
+def errors_of(metrics, acc, pot, ra, rp):
+    ea = metrics.rel_errors(acc, ra)
+    out = {"acc_rel_rms": ea["rel_rms"], "acc_e_max": ea["e_max"], "acc_normwise": ea["normwise"],
+           "sample": int(ea["count"])}
+    if pot is not None:
+        ep = metrics.rel_errors(pot, rp)
+        out.update({"pot_rel_rms": ep["rel_rms"], "pot_e_max": ep["e_max"]})
+    return out
+
+
+def roofline(kind, pairs_per_launch, kernel_ms, kernel_name, traffic=None):
+    achieved = pairs_per_launch * FLOPS[kind] / (kernel_ms * 1e-3) / 1e12
+    peak = peak_pairs(kind) * FLOPS[kind] / 1e12
+    return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+            "frac": achieved / peak, "traffic": traffic, "kernel": kernel_name,
+            "kernel_ms": kernel_ms, "flops_per_pair": FLOPS[kind],
+            "issue_slots_per_pair": SLOTS[kind], "peak_pairs_per_s": peak_pairs(kind)}
+
+
+# --------------------------------------------------------------------------- workloads
+def bench_plummer(args, torch, w):
+    from paper_astro_ph_0703100_amd import _lib, api, ics, metrics
+    n = w.n
+    dt = w.dt or 1.0 / 256
+    pos, vel, mass = ics.plummer(n, seed=w.seed, velocities=(w.name != "plummer_2048"))
+    m32 = mass.astype(np.float32)
+    eps = float(np.float32(w.eps))
+    dev = torch.device("cuda:0")
+    x0 = torch.from_numpy(np.ascontiguousarray(pos.T)).to(dev)
+    v0 = torch.from_numpy(np.ascontiguousarray(vel.T)).to(dev)
+    m = torch.from_numpy(m32).to(dev)
+    p32 = torch.from_numpy(np.ascontiguousarray(pos.T.astype(np.float32))).to(dev)
+    sp = torch.cuda.current_stream().cuda_stream
+    timer = Timer(torch)
+    pairs = float(n) * float(n)
+    res = {}
+    for precision in [s for s in args.modes.split(",") if s]:
+        x, v = x0.clone(), v0.clone()
+        acc, _, _ = api.leapfrog(x, v, m, eps, dt, 0, precision=precision)
+        pot = torch.empty(n, dtype=torch.float64, device=dev)
+        g = api.LeapfrogGraph(x, v, m, eps, dt, 1, acc, pot=pot, precision=precision)
+        for _ in range(args.warmup):
+            g.launch()
+        torch.cuda.synchronize()
+        x.copy_(x0)
+        v.copy_(v0)
+        api.leapfrog(x, v, m, eps, dt, 0, acc=acc, precision=precision)
+        wall, step_ms = timer.run(g.launch, args.steps, warmup=0)
+        g.close()
+        fa = torch.empty((3, n), dtype=torch.float64, device=dev)
+        fp = torch.empty(n, dtype=torch.float64, device=dev)
+        opts = api.make_opts(precision=precision)
+        _, kms = timer.run(lambda: _lib.nbody_force_ex(n, p32.data_ptr(), m.data_ptr(), eps,
+                                                       fa.data_ptr(), fp.data_ptr(), opts, sp),
+                           max(args.steps, 3))
+        a64, p64 = api.force_f64(x0, m, eps, precision=precision)
+        torch.cuda.synchronize()
+        res[precision] = {"wall": wall, "step_ms": step_ms, "kernel_ms": float(np.mean(kms)),
+                          "acc": a64.cpu().numpy().T.copy(), "pot": p64.cpu().numpy().copy()}
+        print("bench: %-8s %d steps  %.3f ms/step (wall)  force kernel %.3f ms"
+              % (precision, args.steps, wall / args.steps * 1e3, np.mean(kms)),
+              file=sys.stderr, flush=True)
+    cpu, errors = None, {}
+    if not args.no_cpu_baseline:
+        import oracle
+        k = n if args.cpu_sample <= 0 else min(n, args.cpu_sample)
+        idx = np.arange(n) if k == n else ics.sample_indices(n, k, seed=w.seed + 1000)
+        t0 = time.perf_counter()
+        ra, rp = oracle.force_sampled(pos, m32.astype(np.float64), eps, idx)
+        ct = time.perf_counter() - t0
+        cpu = {"value": k * pairs / n / ct, "unit": "pair-interactions/s",
+               "cores": oracle.threads(), "kind": "oracle",
+               "sample": "force+potential of %d i-particles from all %d particles of the same "
+                         "sphere at the initial positions, FP64 (%.1f s)" % (k, n, ct)}
+        for p, r in res.items():
+            errors[p] = errors_of(metrics, r["acc"][idx], r["pot"][idx], ra, rp)
+    head = next(iter(res))
+    r0 = res[head]
+    traffic = committed_traffic() if w.name == "plummer_131072" else None
+    return {
+        "value": pairs * args.steps / r0["wall"], "ms_per_step": r0["wall"] / args.steps * 1e3,
+        "config": {"workload": w.name, "n": n, "eps": eps, "seed": w.seed, "dt": dt,
+                   "precision": head,
+                   "step": "one graph-replayed KDK leapfrog step: FP64 state, FP32 pair "
+                           "arithmetic relative to the system centre, one N^2 force+potential "
+                           "evaluation", "description": w.description},
+        "roofline": roofline("gravity", pairs, r0["kernel_ms"],
+                             "tile_kernel<Gravity> (+ finalize_kernel)", traffic),
+        "cpu_baseline": cpu,
+        "modes": {p: {"value": pairs * args.steps / r["wall"],
+                      "ms_per_step": r["wall"] / args.steps * 1e3,
+                      "step_ms_events": float(np.mean(r["step_ms"])),
+                      "force_kernel_ms": r["kernel_ms"],
+                      "roofline_frac": pairs / (r["kernel_ms"] * 1e-3) / peak_pairs("gravity"),
+                      "errors": errors.get(p)} for p, r in res.items()},
+        "gflops_38": pairs * 38 / (r0["kernel_ms"] * 1e-3) / 1e9,
+        "gflops_20": pairs * 20 / (r0["kernel_ms"] * 1e-3) / 1e9,
+    }
+
+
+def bench_stress(args, torch, w):
+    from paper_astro_ph_0703100_amd import api, ics, metrics
+    n = w.n
+    pos, mass, core = ics.stress_system(n, seed=w.seed)
+    dev = torch.device("cuda:0")
+    perm = api.morton_order(torch.from_numpy(np.ascontiguousarray(pos.T)).to(dev))
+    perm = perm.cpu().numpy().astype(np.int64)
+    pos, mass, core = pos[perm], mass[perm], core[perm]
+    m32 = mass.astype(np.float32)
+    eps = float(np.float32(w.eps))
+    x = torch.from_numpy(np.ascontiguousarray(pos.T)).to(dev)
+    m = torch.from_numpy(m32).to(dev)
+    timer = Timer(torch)
+    pairs = float(n) * float(n)
+    res = {}
+    for precision in [s for s in args.modes.split(",") if s]:
+        out = {}
+        for centre in ("tile", "system"):
+            acc = torch.empty((3, n), dtype=torch.float64, device=dev)
+            pot = torch.empty(n, dtype=torch.float64, device=dev)
+            call = lambda: api.force_f64(x, m, eps, precision=precision, centre=centre,
+                                         out=(acc, pot))
+            wall, kms = timer.run(call, args.steps, warmup=args.warmup)
+            out[centre] = {"wall": wall, "kernel_ms": float(np.mean(kms)),
+                           "acc": acc.cpu().numpy().T.copy(), "pot": pot.cpu().numpy().copy()}
+        res[precision] = out
+        print("bench: %-8s tile %.3f ms  system %.3f ms" % (precision, out["tile"]["kernel_ms"],
+              out["system"]["kernel_ms"]), file=sys.stderr, flush=True)
+    cpu, errors = None, {}
+    if not args.no_cpu_baseline:
+        import oracle
+        k = args.cpu_sample if args.cpu_sample > 0 else 2048
+        idx = ics.stratified_indices(core, k, seed=w.seed + 1000)
+        t0 = time.perf_counter()
+        ra, rp = oracle.force_sampled(pos, m32.astype(np.float64), eps, idx)
+        ct = time.perf_counter() - t0
+        cpu = {"value": idx.size * pairs / n / ct, "unit": "pair-interactions/s",
+               "cores": oracle.threads(), "kind": "oracle",
+               "sample": "%d stratified i-particles (half core, half halo) from all %d, FP64 "
+                         "(%.1f s)" % (idx.size, n, ct)}
+        for p, out in res.items():
+            for centre, r in out.items():
+                errors["%s/%s" % (p, centre)] = errors_of(metrics, r["acc"][idx], r["pot"][idx],
+                                                          ra, rp)
+    head = next(iter(res))
+    r0 = res[head]["tile"]
+    return {
+        "value": pairs * args.steps / r0["wall"], "ms_per_step": r0["wall"] / args.steps * 1e3,
+        "config": {"workload": w.name, "n": n, "eps": eps, "seed": w.seed, "precision": head,
+                   "centre": "tile (Morton order)",
+                   "step": "one force+potential evaluation from FP64 positions, FP32 pair "
+                           "arithmetic relative to per-i-tile FP64 centres",
+                   "description": w.description},
+        "roofline": roofline("gravity", pairs, r0["kernel_ms"],
+                             "tile_kernel<GravityTile> (+ centres, finalize)"),
+        "cpu_baseline": cpu,
+        "modes": {"%s/%s" % (p, c): {"value": pairs * args.steps / r["wall"],
+                                     "kernel_ms": r["kernel_ms"],
+                                     "errors": errors.get("%s/%s" % (p, c))}
+                  for p, out in res.items() for c, r in out.items()},
+    }
+
+
+def bench_clusters(args, torch, w):
+    from paper_astro_ph_0703100_amd import api, ics, metrics
+    b = ics.cluster_batch(w.n, seed=w.seed, eps=w.eps)
+    dev = torch.device("cuda:0")
+    m32 = b.mass.astype(np.float32)
+    x0 = torch.from_numpy(np.ascontiguousarray(b.pos.T)).to(dev)
+    v0 = torch.from_numpy(np.ascontiguousarray(b.vel.T)).to(dev)
+    m = torch.from_numpy(m32).to(dev)
+    e = torch.from_numpy(b.eps.astype(np.float32)).to(dev)
+    p32 = torch.from_numpy(np.ascontiguousarray(b.pos.T.astype(np.float32))).to(dev)
+    timer = Timer(torch)
+    res = {}
+    pairs = None
+    for precision in [s for s in args.modes.split(",") if s]:
+        plan = api.BatchPlan(b.offsets, precision=precision)
+        info = plan.info()
+        pairs = float(info["pairs"])
+        x, v = x0.clone(), v0.clone()
+        acc, _ = plan.leapfrog(x, v, m, e, w.dt, 0)
+        g = plan.graph(x, v, m, e, w.dt, 1, acc)
+        for _ in range(args.warmup):
+            g.launch()
+        torch.cuda.synchronize()
+        wall, step_ms = timer.run(g.launch, args.steps, warmup=0)
+        g.close()
+        _, kms = timer.run(lambda: plan.force(p32, m, e), max(args.steps, 3))
+        a, _ = plan.force_f64(x0, m, e)
+        torch.cuda.synchronize()
+        res[precision] = {"wall": wall, "step_ms": step_ms, "kernel_ms": float(np.mean(kms)),
+                          "acc": a.cpu().numpy().T.copy(), "info": info}
+        plan.close()
+        print("bench: %-8s %d steps  %.3f ms/step  batched force %.3f ms  %s"
+              % (precision, args.steps, wall / args.steps * 1e3, np.mean(kms), info),
+              file=sys.stderr, flush=True)
+    cpu, errors = None, {}
+    if not args.no_cpu_baseline:
+        import oracle
+        rng = np.random.default_rng(w.seed + 1000)
+        pick = sorted(set([int(np.argmin(b.sizes)), int(np.argmax(b.sizes))] +
+                          list(rng.choice(b.nsys, size=14, replace=False))))
+        t0 = time.perf_counter()
+        refs = {k: oracle.force_all(b.pos[b.offsets[k]:b.offsets[k + 1]],
+                                    m32[b.offsets[k]:b.offsets[k + 1]].astype(np.float64),
+                                    float(np.float32(w.eps)))[0] for k in pick}
+        ct = time.perf_counter() - t0
+        cpairs = float(sum(int(b.sizes[k]) ** 2 for k in pick))
+        cpu = {"value": cpairs / ct, "unit": "pair-interactions/s", "cores": oracle.threads(),
+               "kind": "oracle", "sample": "%d of the clusters (incl. smallest and largest), "
+                                           "%.3g pairs, FP64 (%.1f s)" % (len(pick), cpairs, ct)}
+        for p, r in res.items():
+            sel = np.concatenate([np.arange(b.offsets[k], b.offsets[k + 1]) for k in pick])
+            ref = np.concatenate([refs[k] for k in pick])
+            errors[p] = errors_of(metrics, r["acc"][sel], None, ref, None)
+    head = next(iter(res))
+    r0 = res[head]
+    return {
+        "value": pairs * args.steps / r0["wall"], "ms_per_step": r0["wall"] / args.steps * 1e3,
+        "config": {"workload": w.name, "systems": w.n, "particles": int(b.offsets[-1]),
+                   "pairs_per_step": pairs, "eps": w.eps, "dt": w.dt, "precision": head,
+                   "step": "one graph-replayed batched KDK step (one persistent launch over "
+                           "cost-sorted work items)", "plan": r0["info"],
+                   "description": w.description},
+        "roofline": roofline("gravity", pairs, r0["kernel_ms"],
+                             "persistent_kernel<Gravity> (+ batched finalize)"),
+        "cpu_baseline": cpu,
+        "modes": {p: {"value": pairs * args.steps / r["wall"],
+                      "ms_per_step": r["wall"] / args.steps * 1e3,
+                      "force_kernel_ms": r["kernel_ms"], "errors": errors.get(p)}
+                  for p, r in res.items()},
+    }
+
+
+def bench_adjoint(args, torch, w):
+    from paper_astro_ph_0703100_amd import _lib, api, autograd, ics, metrics
+    n = w.n
+    x0, v0, mass = ics.plummer(n, seed=w.seed)
+    m64 = mass.astype(np.float32).astype(np.float64)
+    y = ics.perturbed_target(x0, seed=5001)
+    eps = float(np.float32(w.eps))
+    dev = torch.device("cuda:0")
+    xt = torch.from_numpy(np.ascontiguousarray(x0.T)).to(dev)
+    vt = torch.from_numpy(np.ascontiguousarray(v0.T)).to(dev)
+    mt = torch.from_numpy(m64).to(dev)
+    yt = torch.from_numpy(np.ascontiguousarray(y.T)).to(dev)
+    timer = Timer(torch)
+    state = {}
+
+    def step():
+        xi = xt.clone().requires_grad_(True)
+        vi = vt.clone().requires_grad_(True)
+        mi = mt.clone().requires_grad_(True)
+        xT, _ = autograd.rollout(xi, vi, mi, eps, w.dt, w.steps)
+        loss = ((xT - yt) ** 2).sum() / n
+        loss.backward()
+        state["g"] = (float(loss.detach()), xi.grad, vi.grad, mi.grad)
+
+    wall, step_ms = timer.run(step, args.steps, warmup=args.warmup)
+    # The adjoint kernel alone.
+    p32 = torch.from_numpy(np.ascontiguousarray(x0.T.astype(np.float32))).to(dev)
+    m32 = mt.float()
+    g = torch.from_numpy(np.random.default_rng(1).standard_normal((3, n))).to(dev)
+    gx = torch.empty((3, n), dtype=torch.float64, device=dev)
+    gm = torch.empty(n, dtype=torch.float64, device=dev)
+    opts = api.make_opts()
+    sp = torch.cuda.current_stream().cuda_stream
+    _, kms = timer.run(lambda: _lib.nbody_force_vjp(n, p32.data_ptr(), m32.data_ptr(), eps,
+                                                    g.data_ptr(), None, gx.data_ptr(),
+                                                    gm.data_ptr(), opts, sp), 8)
+    pairs_step = float(n) * n * 2 * (w.steps + 1)
+    print("bench: rollout+gradient %.3f ms/step, adjoint kernel %.3f ms" %
+          (wall / args.steps * 1e3, np.mean(kms)), file=sys.stderr, flush=True)
+    cpu, errors = None, {}
+    if not args.no_cpu_baseline:
+        import oracle
+        t0 = time.perf_counter()
+        lo, rx, rv, rm = oracle.rollout_loss_grad(x0, v0, m64, eps, w.dt, w.steps, y)
+        ct = time.perf_counter() - t0
+        cpu = {"value": pairs_step / ct, "unit": "pair-interactions/s", "cores": oracle.threads(),
+               "kind": "oracle", "sample": "the whole loss and gradient (%d forward + %d adjoint "
+                                           "evaluations of %d^2 pairs), FP64 (%.1f s)"
+                                           % (w.steps + 1, w.steps + 1, n, ct)}
+        loss, gxg, gvg, gmg = state["g"]
+        errors["comp"] = {
+            "loss_rel": abs(loss - lo) / abs(lo),
+            "grad_x0_normwise": metrics.rel_errors(gxg.cpu().numpy().T, rx)["normwise"],
+            "grad_v0_normwise": metrics.rel_errors(gvg.cpu().numpy().T, rv)["normwise"],
+            "grad_m_normwise": metrics.rel_errors(gmg.cpu().numpy(), rm)["normwise"]}
+    return {
+        "value": pairs_step * args.steps / wall, "ms_per_step": wall / args.steps * 1e3,
+        "config": {"workload": w.name, "n": n, "eps": eps, "dt": w.dt, "steps": w.steps,
+                   "precision": "comp",
+                   "step": "loss and gradient: %d-step checkpointed KDK rollout and the reverse "
+                           "pass with the adjoint kernel; pairs counted: forward + adjoint"
+                           % w.steps, "description": w.description},
+        "roofline": roofline("adjoint", float(n) * n, float(np.mean(kms)),
+                             "tile_kernel<Adjoint> (+ finalize)"),
+        "cpu_baseline": cpu,
+        "modes": {"comp": {"value": pairs_step * args.steps / wall,
+                           "adjoint_kernel_ms": float(np.mean(kms)),
+                           "errors": errors.get("comp")}},
+    }
 
 
 def main():
@@ -80,151 +453,38 @@ def main():
 
     import torch
 
-    from paper_astro_ph_0703100_amd import _lib, api, ics, metrics
-
-    w = ics.WORKLOADS[args.workload]
-    n = w.n
-    dt = w.dt or 1.0 / 256
-    pos, vel, mass = ics.plummer(n, seed=w.seed)
-    m32 = mass.astype(np.float32)
-    eps = float(np.float32(w.eps))
-    dev = torch.device("cuda:0")
-    x0 = torch.from_numpy(np.ascontiguousarray(pos.T)).to(dev)
-    v0 = torch.from_numpy(np.ascontiguousarray(vel.T)).to(dev)
-    m = torch.from_numpy(m32).to(dev)
-    p32 = torch.from_numpy(np.ascontiguousarray(pos.T.astype(np.float32))).to(dev)
-    stream = torch.cuda.current_stream()
-    sp = stream.cuda_stream
-    pairs = float(n) * float(n)
-    modes = [s for s in args.modes.split(",") if s]
-
-    def timed_steps(precision: str):
-        """K graph-replayed KDK steps from the initial state; wall time and per-step ms."""
-        x, v = x0.clone(), v0.clone()
-        acc, _, _ = api.leapfrog(x, v, m, eps, dt, 0, precision=precision)
-        pot = torch.empty(n, dtype=torch.float64, device=dev)
-        g = api.LeapfrogGraph(x, v, m, eps, dt, 1, acc, pot=pot, precision=precision)
-        for _ in range(args.warmup):
-            g.launch()
-        torch.cuda.synchronize()
-        x.copy_(x0)
-        v.copy_(v0)
-        api.leapfrog(x, v, m, eps, dt, 0, acc=acc, precision=precision)
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in range(args.steps)]
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for k in range(args.steps):
-            ev[k][0].record(stream)
-            g.launch()
-            ev[k][1].record(stream)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        g.close()
-        return wall, [a.elapsed_time(b) for a, b in ev]
-
-    def timed_force(precision: str, reps: int):
-        """Events around standalone force evaluations (pair kernel + FP64 finalize)."""
-        acc = torch.empty((3, n), dtype=torch.float64, device=dev)
-        pot = torch.empty(n, dtype=torch.float64, device=dev)
-        opts = api.make_opts(precision=precision)
-        call = lambda: _lib.nbody_force_ex(n, p32.data_ptr(), m.data_ptr(), eps, acc.data_ptr(),
-                                           pot.data_ptr(), opts, sp)
-        call()
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in range(reps)]
-        torch.cuda.synchronize()
-        for k in range(reps):
-            ev[k][0].record(stream)
-            call()
-            ev[k][1].record(stream)
-        torch.cuda.synchronize()
-        return [a.elapsed_time(b) for a, b in ev]
-
-    def force_f64(precision: str):
-        acc, pot = api.force_f64(x0, m, eps, precision=precision)
-        torch.cuda.synchronize()
-        return acc.cpu().numpy().T.copy(), pot.cpu().numpy().copy()
+    from paper_astro_ph_0703100_amd import ics
 
     if args.calib_copy_mb > 0:
         nb = args.calib_copy_mb * (1 << 20) // 4
-        src = torch.ones(nb, dtype=torch.float32, device=dev)
+        src = torch.ones(nb, dtype=torch.float32, device="cuda:0")
+        evict = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")  # 1 GiB through the caches
+        del evict
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
 
-    res = {}
-    for precision in modes:
-        wall, step_ms = timed_steps(precision)
-        kms = timed_force(precision, max(args.steps, 3))
-        a_np, p_np = force_f64(precision)
-        res[precision] = {"wall": wall, "step_ms": step_ms, "kernel_ms": float(np.mean(kms)),
-                          "acc": a_np, "pot": p_np}
-        print("bench: %-8s %d steps  %.3f ms/step (wall)  force kernel %.3f ms" %
-              (precision, args.steps, wall / args.steps * 1e3, np.mean(kms)),
-              file=sys.stderr, flush=True)
-
-    cpu = None
-    errors = {}
-    if not args.no_cpu_baseline:
-        import oracle
-        k = n if args.cpu_sample <= 0 else min(n, args.cpu_sample)
-        idx = np.arange(n) if k == n else ics.sample_indices(n, k, seed=w.seed + 1000)
-        t0 = time.perf_counter()
-        ra, rp = oracle.force_sampled(pos, m32.astype(np.float64), eps, idx)
-        ct = time.perf_counter() - t0
-        cpu = {"value": k * float(n) / ct, "unit": "pair-interactions/s",
-               "cores": oracle.threads(), "kind": "oracle",
-               "sample": "force+potential of %d i-particles from all %d particles of the same "
-                         "sphere at the initial positions, FP64 (%.1f s)" % (k, n, ct)}
-        for precision, r in res.items():
-            ea = metrics.rel_errors(r["acc"][idx], ra)
-            ep = metrics.rel_errors(r["pot"][idx], rp)
-            errors[precision] = {"acc_rel_rms": ea["rel_rms"], "acc_e_max": ea["e_max"],
-                                 "acc_normwise": ea["normwise"], "pot_rel_rms": ep["rel_rms"],
-                                 "pot_e_max": ep["e_max"], "sample": int(idx.size)}
-
-    head = modes[0]
-    r0 = res[head]
-    k_ms = r0["kernel_ms"]
-    achieved_tf = pairs * FLOPS_PER_PAIR / (k_ms * 1e-3) / 1e12
-    peak_tf = peak_pairs_per_s() * FLOPS_PER_PAIR / 1e12
+    w = ics.WORKLOADS[args.workload]
+    fn = {"plummer_131072": bench_plummer, "plummer_2048": bench_plummer,
+          "stress_1m": bench_stress, "clusters_2048": bench_clusters,
+          "adjoint_16384": bench_adjoint}[w.name]
+    body = fn(args, torch, w)
     line = {
-        "metric": METRIC,
-        "value": pairs * args.steps / r0["wall"],
+        "metric": METRIC if w.name == "plummer_131072" else "pair interactions/s, " + w.name,
+        "value": body["value"],
         "unit": "pair-interactions/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": r0["wall"] / args.steps * 1e3,
+        "ms_per_step": body["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": w.name, "n": n, "eps": eps, "seed": w.seed, "dt": dt,
-                   "precision": head,
-                   "step": "one graph-replayed KDK leapfrog step: FP64 state, FP32 pair "
-                           "arithmetic relative to the system centre, one N^2 force+potential "
-                           "evaluation",
-                   "description": w.description},
-        "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": peak_tf, "unit": "TFLOP/s",
-                     "frac": achieved_tf / peak_tf, "traffic": None,
-                     "kernel": "pair_kernel (+ finalize_kernel, <0.3%)", "kernel_ms": k_ms,
-                     "flops_per_pair": FLOPS_PER_PAIR,
-                     "issue_slots_per_pair": VALU_PER_PAIR + RSQ_SLOTS,
-                     "peak_pairs_per_s": peak_pairs_per_s()},
-        "cpu_baseline": cpu,
-        "modes": {p: {"value": pairs * args.steps / r["wall"],
-                      "ms_per_step": r["wall"] / args.steps * 1e3,
-                      "step_ms_events": float(np.mean(r["step_ms"])),
-                      "force_kernel_ms": r["kernel_ms"],
-                      "roofline_frac": pairs / (r["kernel_ms"] * 1e-3) / peak_pairs_per_s(),
-                      "errors": errors.get(p)} for p, r in res.items()},
-        "gflops_38": metrics.gflops(pairs, k_ms * 1e-3, 38),
-        "gflops_20": metrics.gflops(pairs, k_ms * 1e-3, 20),
     }
+    line.update({k: v for k, v in body.items() if k not in ("value", "ms_per_step")})
     print(json.dumps(line), flush=True)
 
 
