@@ -10,6 +10,12 @@ Parity status of each function (what pins it; the pins are in tests/test_oracle.
   force_all / force_sampled / force_ij : two-body closed form, 50-digit brute
       force, momentum conservation, Plummer mean field, exact power-of-two
       scaling, coincident pair, n = 1, permutation, Table 2 error magnitudes.
+  force_ij with eps_i : two-body closed forms with a different softening per
+      i-particle (including eps = 0), 50-digit brute force on separate i- and
+      j-sets with per-i softening.
+  force_jerk          : two-body closed form, central time differences of
+      force_all along x + v t, 50-digit brute force, sum_i m_i jerk_i = 0,
+      exact power-of-two scaling of v, Galilean invariance.
   vjp                 : central finite differences of force_all, translation
       invariance, degree-1 homogeneity in the masses.
   rollout             : time reversibility, second-order energy error, two-body
@@ -56,6 +62,9 @@ def _load():
             build()
             lib = ctypes.CDLL(_LIB)
             lib.oracle_force.argtypes = [_I64, _D, _D, _I64, _D, _L, ctypes.c_double, _D, _D]
+            lib.oracle_force_epsi.argtypes = [_I64, _D, _D, _I64, _D, _D, _D, _D]
+            lib.oracle_force_jerk.argtypes = [_I64, _D, _D, _D, _I64, _D, _D, _L, ctypes.c_double,
+                                              _D, _D, _D]
             lib.oracle_force_all.argtypes = [_I64, _D, _D, ctypes.c_double, _D, _D]
             lib.oracle_force_sampled.argtypes = [_I64, _D, _D, ctypes.c_double, _I64, _L, _D, _D]
             lib.oracle_vjp.argtypes = [_I64, _D, _D, ctypes.c_double, _D, _D, _D, _D]
@@ -115,20 +124,51 @@ def force_sampled(x, m, eps, idx):
     return acc, pot
 
 
-def force_ij(xj, mj, xi, eps, self_index=None):
+def force_ij(xj, mj, xi, eps, self_index=None, eps_i=None):
     """Forces on separate i-particles ``xi`` from j-particles (``xj``, ``mj``).
 
     ``self_index[i]`` names a j to leave out for i (or -1); None leaves none out.
+    ``eps_i`` (one softening length per i-particle) replaces ``eps``; it cannot be
+    combined with ``self_index``.
     """
     xj = _f64(xj)
     xi = _f64(xi)
     nj, ni = xj.shape[0], xi.shape[0]
     mj = _f64(mj, (nj,))
+    if eps_i is not None:
+        if self_index is not None:
+            raise ValueError("eps_i and self_index cannot be combined")
+        ei = _f64(eps_i, (ni,))
+        acc = np.empty((ni, 3))
+        pot = np.empty(ni)
+        _load().oracle_force_epsi(nj, _p(xj), _p(mj), ni, _p(xi), _p(ei), _p(acc), _p(pot))
+        return acc, pot
     si = None if self_index is None else np.ascontiguousarray(self_index, dtype=np.int64)
     acc = np.empty((ni, 3))
     pot = np.empty(ni)
     _load().oracle_force(nj, _p(xj), _p(mj), ni, _p(xi), _p(si, _L), float(eps), _p(acc), _p(pot))
     return acc, pot
+
+
+def force_jerk(x, v, m, eps, idx=None):
+    """(acc, jerk, pot) of every particle (or of the sampled ``idx``) from all others,
+    self pair excluded; ``x``, ``v`` are ``(n, 3)``."""
+    x = _f64(x)
+    n = x.shape[0]
+    v = _f64(v, (n, 3))
+    m = _f64(m, (n,))
+    if idx is None:
+        idx = np.arange(n, dtype=np.int64)
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    if idx.size and (idx.min() < 0 or idx.max() >= n):
+        raise IndexError("sample index out of range")
+    xi = np.ascontiguousarray(x[idx])
+    vi = np.ascontiguousarray(v[idx])
+    k = idx.size
+    acc, jerk, pot = np.empty((k, 3)), np.empty((k, 3)), np.empty(k)
+    _load().oracle_force_jerk(n, _p(x), _p(v), _p(m), k, _p(xi), _p(vi), _p(idx, _L), float(eps),
+                              _p(acc), _p(jerk), _p(pot))
+    return acc, jerk, pot
 
 
 def vjp(x, m, eps, g_acc, g_pot=None):

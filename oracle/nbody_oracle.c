@@ -65,6 +65,37 @@ OR_EXPORT void oracle_force(int64_t nj, const double *xj, const double *mj,
     }
 }
 
+/* Separate i- and j-sets with a softening length per i-particle (the paper's
+ * library takes separate i and j arrays, Sec. 3.1, and its driver keeps eps^2 per
+ * i-particle, Appendix A).  Every pair is summed; eps_i[i] may be 0. */
+OR_EXPORT void oracle_force_epsi(int64_t nj, const double *xj, const double *mj,
+                                 int64_t ni, const double *xi, const double *eps_i,
+                                 double *acc, double *pot)
+{
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int64_t i = 0; i < ni; ++i) {
+        const double eps2 = eps_i[i] * eps_i[i];
+        double ax = 0.0, ay = 0.0, az = 0.0, ph = 0.0;
+        for (int64_t j = 0; j < nj; ++j) {
+            const double dx = xj[3 * j + 0] - xi[3 * i + 0];
+            const double dy = xj[3 * j + 1] - xi[3 * i + 1];
+            const double dz = xj[3 * j + 2] - xi[3 * i + 2];
+            const double s2 = dx * dx + dy * dy + dz * dz + eps2;
+            const double s = sqrt(s2);
+            const double s3 = s2 * s;
+            ax += mj[j] * dx / s3;
+            ay += mj[j] * dy / s3;
+            az += mj[j] * dz / s3;
+            ph -= mj[j] / s;
+        }
+        acc[3 * i + 0] = ax;
+        acc[3 * i + 1] = ay;
+        acc[3 * i + 2] = az;
+        if (pot)
+            pot[i] = ph;
+    }
+}
+
 /* All-pairs convenience: i-set == j-set, self pair excluded. */
 OR_EXPORT void oracle_force_all(int64_t n, const double *x, const double *m,
                                 double eps, double *acc, double *pot)
@@ -86,6 +117,52 @@ OR_EXPORT void oracle_force_sampled(int64_t n, const double *x, const double *m,
         memcpy(xi + 3 * t, x + 3 * idx[t], 3 * sizeof(double));
     oracle_force(n, x, m, k, xi, idx, eps, acc, pot);
     free(xi);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Force, jerk and potential (the force-jerk-potential pipeline of Appendix A, */
+/* the interaction a fourth-order Hermite integrator needs, Sec. 5.1).  With   */
+/* d = x_j - x_i, w = v_j - v_i and s^2 = |d|^2 + eps^2, the time derivative   */
+/* of the pair acceleration m_j d / s^3 along the motion is                     */
+/*   jerk_ij = m_j ( w / s^3 - 3 (d . w) d / s^5 ).                              */
+/* self[i] is the j to skip for i, or -1; self may be NULL.  pot may be NULL.   */
+/* ------------------------------------------------------------------------- */
+OR_EXPORT void oracle_force_jerk(int64_t nj, const double *xj, const double *vj,
+                                 const double *mj, int64_t ni, const double *xi,
+                                 const double *vi, const int64_t *self, double eps,
+                                 double *acc, double *jerk, double *pot)
+{
+    const double eps2 = eps * eps;
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int64_t i = 0; i < ni; ++i) {
+        const int64_t skip = self ? self[i] : -1;
+        double a[3] = {0.0, 0.0, 0.0}, jk[3] = {0.0, 0.0, 0.0}, ph = 0.0;
+        for (int64_t j = 0; j < nj; ++j) {
+            if (j == skip)
+                continue;
+            double d[3], w[3];
+            for (int c = 0; c < 3; ++c) {
+                d[c] = xj[3 * j + c] - xi[3 * i + c];
+                w[c] = vj[3 * j + c] - vi[3 * i + c];
+            }
+            const double s2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + eps2;
+            const double s = sqrt(s2);
+            const double s3 = s2 * s;
+            const double s5 = s3 * s2;
+            const double dw = d[0] * w[0] + d[1] * w[1] + d[2] * w[2];
+            for (int c = 0; c < 3; ++c) {
+                a[c] += mj[j] * d[c] / s3;
+                jk[c] += mj[j] * (w[c] / s3 - 3.0 * dw * d[c] / s5);
+            }
+            ph -= mj[j] / s;
+        }
+        for (int c = 0; c < 3; ++c) {
+            acc[3 * i + c] = a[c];
+            jerk[3 * i + c] = jk[c];
+        }
+        if (pot)
+            pot[i] = ph;
+    }
 }
 
 /* ------------------------------------------------------------------------- */

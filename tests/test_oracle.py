@@ -137,6 +137,122 @@ def test_sampled_and_ij_forms_agree_with_all_pairs():
     np.testing.assert_allclose(p4, pot[idx] - m[idx] / 0.03, rtol=1e-13)
 
 
+def test_separate_sets_with_per_i_softening_closed_form():
+    # j at (1, 2, 2) (|d| = 3) with mass 0.5, seen from three i-particles at the origin
+    # with eps = 4, 0 and 0 (the last one shifted to (1, 2, 0): |d| = 2):
+    # a = m d / (|d|^2 + eps^2)^{3/2}, phi = -m / sqrt(|d|^2 + eps^2).
+    xj = np.array([[1.0, 2.0, 2.0]])
+    mj = np.array([0.5])
+    xi = np.array([[0.0, 0.0, 0.0], [0.0, 0.0, 0.0], [1.0, 2.0, 0.0]])
+    acc, pot = oracle.force_ij(xj, mj, xi, None, eps_i=np.array([4.0, 0.0, 0.0]))
+    np.testing.assert_allclose(acc[0], [0.5 / 125, 1.0 / 125, 1.0 / 125], rtol=2e-16, atol=0)
+    np.testing.assert_allclose(acc[1], [0.5 / 27, 1.0 / 27, 1.0 / 27], rtol=2e-16, atol=0)
+    np.testing.assert_allclose(acc[2], [0.0, 0.0, 1.0 / 8], rtol=2e-16, atol=0)
+    np.testing.assert_allclose(pot, [-0.1, -0.5 / 3, -0.25], rtol=2e-16)
+    # No j-particles: zeros.
+    acc, pot = oracle.force_ij(np.zeros((0, 3)), np.zeros(0), xi, None, eps_i=np.ones(3))
+    assert np.all(acc == 0.0) and np.all(pot == 0.0)
+
+
+def test_separate_sets_with_per_i_softening_against_decimal():
+    rng = np.random.default_rng(21)
+    xi, xj = rng.standard_normal((7, 3)), rng.standard_normal((11, 3))
+    mj = rng.uniform(0.1, 1.0, 11)
+    eps_i = rng.uniform(0.0, 0.3, 7)
+    eps_i[2] = 0.0
+    acc, pot = oracle.force_ij(xj, mj, xi, None, eps_i=eps_i)
+    getcontext().prec = 50
+    for i in range(7):
+        a = [Decimal(0)] * 3
+        p = Decimal(0)
+        e2 = Decimal(float(eps_i[i])) ** 2
+        for j in range(11):
+            d = [Decimal(float(xj[j, c])) - Decimal(float(xi[i, c])) for c in range(3)]
+            s2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + e2
+            s = s2.sqrt()
+            for c in range(3):
+                a[c] += Decimal(float(mj[j])) * d[c] / (s2 * s)
+            p -= Decimal(float(mj[j])) / s
+        np.testing.assert_allclose(acc[i], [float(v) for v in a], rtol=1e-13)
+        assert abs(pot[i] - float(p)) <= 1e-14 * abs(float(p))
+
+
+# --------------------------------------------------------------------------- jerk
+def test_jerk_two_body_closed_form():
+    # d = (1, 2, 2), eps = 4: s = 5; w = v_2 - v_1 = (0.5, -1, 0.25), d.w = -1, so
+    # jerk_1 = m_2 (w / 125 + 3 d / 3125) and jerk_2 = -m_1 (w / 125 + 3 d / 3125).
+    x = np.array([[0.0, 0.0, 0.0], [1.0, 2.0, 2.0]])
+    v = np.array([[0.0, 0.0, 0.0], [0.5, -1.0, 0.25]])
+    m = np.array([0.25, 0.5])
+    acc, jerk, pot = oracle.force_jerk(x, v, m, 4.0)
+    base = np.array([0.004 + 0.00096, -0.008 + 0.00192, 0.002 + 0.00192])
+    np.testing.assert_allclose(jerk[0], 0.5 * base, rtol=1e-15, atol=0)
+    np.testing.assert_allclose(jerk[1], -0.25 * base, rtol=1e-15, atol=0)
+    np.testing.assert_allclose(acc[0], [0.004, 0.008, 0.008], rtol=2e-16, atol=0)
+    np.testing.assert_allclose(pot, [-0.1, -0.05], rtol=2e-16)
+
+
+def test_jerk_is_the_time_derivative_of_the_force():
+    # Along straight-line motion x(t) = x + v t, jerk = d a / dt; central differences
+    # of the (separately pinned) force sum, h = 1e-5, truncation error O(h^2).
+    x, v, m = ics.plummer(64, seed=31)
+    eps, h = 0.05, 1e-5
+    _, jerk, _ = oracle.force_jerk(x, v, m, eps)
+    ap, _ = oracle.force_all(x + h * v, m, eps)
+    am, _ = oracle.force_all(x - h * v, m, eps)
+    fd = (ap - am) / (2 * h)
+    assert rel_errors(jerk, fd)["normwise"] < 1e-8
+    assert rel_errors(jerk, fd)["rel_rms"] < 1e-7
+
+
+def test_jerk_against_decimal():
+    rng = np.random.default_rng(33)
+    n = 6
+    x, v = rng.standard_normal((n, 3)), rng.standard_normal((n, 3))
+    m = rng.uniform(0.1, 1.0, n)
+    eps = 0.1
+    _, jerk, _ = oracle.force_jerk(x, v, m, eps)
+    getcontext().prec = 50
+    D = lambda a: Decimal(float(a))
+    for i in range(n):
+        jk = [Decimal(0)] * 3
+        for j in range(n):
+            if j == i:
+                continue
+            d = [D(x[j, c]) - D(x[i, c]) for c in range(3)]
+            w = [D(v[j, c]) - D(v[i, c]) for c in range(3)]
+            s2 = sum(t * t for t in d) + D(eps) ** 2
+            s = s2.sqrt()
+            dw = sum(d[c] * w[c] for c in range(3))
+            for c in range(3):
+                jk[c] += D(m[j]) * (w[c] / (s2 * s) - 3 * dw * d[c] / (s2 * s2 * s))
+        np.testing.assert_allclose(jerk[i], [float(t) for t in jk], rtol=1e-12, atol=1e-14)
+
+
+def test_jerk_invariants():
+    x, v, m = ics.plummer(500, seed=35)
+    m = m * np.random.default_rng(36).uniform(0.5, 1.5, m.size)
+    acc, jerk, pot = oracle.force_jerk(x, v, m, 0.02)
+    # sum_i m_i jerk_i = d/dt sum_i m_i a_i = 0 (pairwise antisymmetry).
+    resid = np.abs((m[:, None] * jerk).sum(0))
+    assert np.all(resid < 1e-13 * (m[:, None] * np.abs(jerk)).sum(0))
+    # v -> 4 v scales the jerk exactly and leaves a and phi alone.
+    a4, j4, p4 = oracle.force_jerk(x, 4.0 * v, m, 0.02)
+    np.testing.assert_array_equal(j4, 4.0 * jerk)
+    np.testing.assert_array_equal(a4, acc)
+    np.testing.assert_array_equal(p4, pot)
+    # A common velocity changes nothing but rounding (Galilean invariance).
+    _, jg, _ = oracle.force_jerk(x, v + np.array([0.3, -0.2, 0.1]), m, 0.02)
+    assert rel_errors(jg, jerk)["normwise"] < 1e-13
+    # The force and potential agree with the force-only sum; a sample agrees with the whole.
+    af, pf = oracle.force_all(x, m, 0.02)
+    np.testing.assert_array_equal(acc, af)
+    np.testing.assert_array_equal(pot, pf)
+    idx = np.array([3, 0, 499])
+    a_s, j_s, p_s = oracle.force_jerk(x, v, m, 0.02, idx=idx)
+    np.testing.assert_array_equal(j_s, jerk[idx])
+
+
 # --------------------------------------------------------------------------- mean field
 def test_shell_theorem_on_plummer_realisation():
     # For a near-spherical particle set the shell-averaged field at radius r is that of
