@@ -100,7 +100,7 @@ NBODY_API size_t nbody_workspace_size(int64_t n, const nbody_opts *opts);
 
 /* ------------------------------------------------------------------------------
  * Forces and potentials, all i against all j of one system (eq. (1)).
- *   n     particles, 0 <= n < 2^31
+ *   n     particles, 0 <= n < 2^30
  *   pos   float [3][n], positions (read)
  *   mass  float [n], masses (read; any sign, zero allowed)
  *   eps   softening length (> 0); the kernel uses fp32(eps * eps)
@@ -121,6 +121,30 @@ NBODY_API nbody_status nbody_force_ex(int64_t n, const float *pos, const float *
  * and for systems far from the origin. */
 NBODY_API nbody_status nbody_force_f64(int64_t n, const double *pos64, const float *mass, float eps,
                              double *acc, double *pot, const nbody_opts *opts, void *stream);
+
+/* ------------------------------------------------------------------------------
+ * Forces and potentials on one set of particles from another (the paper's library
+ * call takes separate i- and j-arrays, Sec. 3.1; its driver keeps eps^2 per
+ * i-particle, Appendix A).  Every (i, j) pair is summed: no pair is treated as a
+ * self pair, so an i-particle that coincides with a j-particle gets 0 acceleration
+ * and -m_j/eps_i potential from it (NaN if eps_i = 0).  Uses: an i-range of a
+ * system against all of it (one GPU's shard of a larger system), interaction lists.
+ *   ni      i-particles, 0 <= ni < 2^30; pos_i float [3][ni] (read)
+ *   eps_i   float [ni] per-i softening lengths (read; each finite and >= 0, not
+ *           checked), or NULL: eps for every i
+ *   nj      j-particles, 0 <= nj < 2^30; pos_j float [3][nj], mass_j float [nj] (read)
+ *   eps     uniform softening (finite, >= 0; eps^2 zero or a normal float)
+ *   acc     double [3][ni] (written); pot double [ni] or NULL (written)
+ *   opts    precision, ipl, jtile, nseg and workspace apply; centre and self_pot are
+ *           ignored (the inputs are FP32 already); NULL = defaults
+ * nj = 0 writes zeros.  Outputs must not alias inputs.  Scratch:
+ * nbody_workspace_size_ij bytes (the per-device cache when opts->workspace is NULL).
+ * ---------------------------------------------------------------------------- */
+NBODY_API nbody_status nbody_force_ij(int64_t ni, const float *pos_i, const float *eps_i,
+                                      int64_t nj, const float *pos_j, const float *mass_j,
+                                      float eps, double *acc, double *pot,
+                                      const nbody_opts *opts, void *stream);
+NBODY_API size_t nbody_workspace_size_ij(int64_t ni, int64_t nj, const nbody_opts *opts);
 
 /* Morton (Z-order) permutation of FP64 positions pos64 double [3][n]: perm int32 [n]
  * (device, written) lists the particle indices in order along the Z-curve of the
@@ -251,6 +275,7 @@ NBODY_API nbody_status nbody_graph_create_leapfrog_batched(const nbody_plan *pla
 #define NBODY_KERNEL_FORCE 0
 #define NBODY_KERNEL_VJP 1
 #define NBODY_KERNEL_BATCHED 2
+#define NBODY_KERNEL_JERK 3
 NBODY_API nbody_status nbody_tune_set(int32_t kernel, int32_t precision, int64_t n, int32_t ipl,
                                       int32_t jtile, int32_t nseg);
 /* shape[0..3) = ipl, jtile, nseg in effect for (kernel, precision, n). */

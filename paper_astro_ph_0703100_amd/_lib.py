@@ -72,6 +72,8 @@ SIGNATURES = {
     "nbody_force": (_I32, [_I64, _P, _P, _F, _P, _P, _P]),
     "nbody_force_ex": (_I32, [_I64, _P, _P, _F, _P, _P, _OPTS, _P]),
     "nbody_force_f64": (_I32, [_I64, _P, _P, _F, _P, _P, _OPTS, _P]),
+    "nbody_force_ij": (_I32, [_I64, _P, _P, _I64, _P, _P, _F, _P, _P, _OPTS, _P]),
+    "nbody_workspace_size_ij": (ctypes.c_size_t, [_I64, _I64, _OPTS]),
     "nbody_leapfrog": (_I32, [_I64, _P, _P, _P, _F, _D, _I32, _P, _P, _P, _I32, _OPTS, _P]),
     "nbody_graph_create_leapfrog": (_I32, [_I64, _P, _P, _P, _F, _D, _I32, _P, _P, _OPTS, _P,
                                            ctypes.POINTER(_P)]),
@@ -99,7 +101,9 @@ SIGNATURES = {
 NBODY_KERNEL_FORCE = 0
 NBODY_KERNEL_VJP = 1
 NBODY_KERNEL_BATCHED = 2
-KERNELS = {"force": NBODY_KERNEL_FORCE, "vjp": NBODY_KERNEL_VJP, "batched": NBODY_KERNEL_BATCHED}
+NBODY_KERNEL_JERK = 3
+KERNELS = {"force": NBODY_KERNEL_FORCE, "vjp": NBODY_KERNEL_VJP, "batched": NBODY_KERNEL_BATCHED,
+           "jerk": NBODY_KERNEL_JERK}
 # Tuning table shipped with the package (measured on MI355X by tune.py); loaded with
 # the library when present.
 TUNING_PATH = os.path.join(_PKG, "tuning_gfx950.json")
@@ -167,6 +171,17 @@ def nbody_force_f64(n, pos64, mass, eps, acc, pot, opts, stream, check=True):
     st = load().nbody_force_f64(n, pos64, mass, eps, acc, pot,
                                 ctypes.byref(opts) if opts is not None else None, stream)
     return _check(st, "nbody_force_f64") if check else st
+
+
+def nbody_force_ij(ni, pos_i, eps_i, nj, pos_j, mass_j, eps, acc, pot, opts, stream, check=True):
+    st = load().nbody_force_ij(ni, pos_i, eps_i, nj, pos_j, mass_j, eps, acc, pot,
+                               ctypes.byref(opts) if opts is not None else None, stream)
+    return _check(st, "nbody_force_ij") if check else st
+
+
+def nbody_workspace_size_ij(ni: int, nj: int, opts: nbody_opts | None) -> int:
+    return int(load().nbody_workspace_size_ij(ni, nj, ctypes.byref(opts) if opts is not None
+                                              else None))
 
 
 def _opt_ref(opts):

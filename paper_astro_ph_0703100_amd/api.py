@@ -84,6 +84,27 @@ def force_f64(pos64: torch.Tensor, mass: torch.Tensor, eps: float, precision: st
     return acc, pot
 
 
+def force_ij(pos_i: torch.Tensor, pos_j: torch.Tensor, mass_j: torch.Tensor, eps: float = 0.0,
+             eps_i: torch.Tensor | None = None, precision: str = "comp", with_pot: bool = True,
+             out=None, **kw):
+    """Accelerations ``[3, ni]`` and potentials ``[ni]`` (float64) on the i-set from the
+    j-set; every pair counts (no self pair).  ``eps_i`` (float32 ``[ni]``) gives a
+    softening per i-particle instead of the uniform ``eps``."""
+    ni = _check_pos(pos_i, torch.float32, "pos_i")
+    nj = _check_pos(pos_j, torch.float32, "pos_j")
+    _check_vec(mass_j, nj, torch.float32, "mass_j")
+    if eps_i is not None:
+        _check_vec(eps_i, ni, torch.float32, "eps_i")
+    acc, pot = out if out is not None else (
+        torch.empty((3, ni), dtype=torch.float64, device=pos_i.device),
+        torch.empty(ni, dtype=torch.float64, device=pos_i.device) if with_pot else None)
+    opts = make_opts(precision=precision, **kw)
+    _lib.nbody_force_ij(ni, pos_i.data_ptr(), eps_i.data_ptr() if eps_i is not None else None,
+                        nj, pos_j.data_ptr(), mass_j.data_ptr(), float(eps), acc.data_ptr(),
+                        pot.data_ptr() if pot is not None else None, opts, stream_ptr())
+    return acc, pot
+
+
 def morton_order(pos64: torch.Tensor) -> torch.Tensor:
     """int32 permutation ``[n]`` ordering the particles along the Z-curve."""
     n = _check_pos(pos64, torch.float64, "pos64")

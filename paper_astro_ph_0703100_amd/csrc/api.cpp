@@ -109,11 +109,13 @@ nbody_status get_workspace(const nbody_opts &o, size_t need, hipStream_t s, void
     return NBODY_OK;
 }
 
-// Launch shape for n particles: explicit options first, then the tuning table, then
-// a default that gives every compute unit several blocks.
-nbody_status choose_cfg(int kernel, int64_t n, int precision, const nbody_opts &o, TileCfg *cfg) {
+// Launch shape for ni i-particles against nj j-particles: explicit options first, then
+// the tuning table (its j-split only when the two sets have the same size, the shape it
+// was measured on), then a default that gives every compute unit several blocks.
+nbody_status choose_cfg_ij(int kernel, int64_t ni, int64_t nj, int precision, const nbody_opts &o,
+                           TileCfg *cfg) {
     TileCfg c;
-    TuneEntry t = tuned_shape(kernel, precision, n);
+    TuneEntry t = tuned_shape(kernel, precision, nj);
     c.ipl = o.ipl ? o.ipl : t.ipl;
     c.jt = o.jtile ? o.jtile : t.jt;
     if (!(c.ipl == 1 || c.ipl == 2 || c.ipl == 4 || c.ipl == 8))
@@ -123,25 +125,28 @@ nbody_status choose_cfg(int kernel, int64_t n, int precision, const nbody_opts &
     if (o.nseg < 0 || o.nseg > kMaxSeg)
         return set_error(NBODY_EINVAL, "nseg must be in [0, " + std::to_string(kMaxSeg) + "]");
     const int64_t itile = (int64_t)kTPB * c.ipl;
-    c.itiles = (int)((n + itile - 1) / itile);
+    c.itiles = (int)((ni + itile - 1) / itile);
     c.npad = (int)(c.itiles * itile);
-    const int64_t jtiles = (n + c.jt - 1) / c.jt;
-    int64_t nseg = o.nseg ? o.nseg : t.nseg;
+    const int64_t jtiles = (nj + c.jt - 1) / c.jt;
+    int64_t nseg = o.nseg ? o.nseg : (ni == nj ? t.nseg : 0);
     if (nseg <= 0) {
         // About 48 blocks per compute unit: enough to keep 8 waves per SIMD busy and to
         // make the last round of blocks short (measured best at 40-64 per CU).
         const int64_t target = (int64_t)device_info().cus * 48;
-        nseg = (target + c.itiles - 1) / c.itiles;
+        nseg = c.itiles > 0 ? (target + c.itiles - 1) / c.itiles : 1;
     }
-    if (nseg > jtiles) nseg = jtiles > 0 ? jtiles : 1;
+    if (nseg > jtiles) nseg = jtiles;
     if (nseg > kMaxSeg) nseg = kMaxSeg;
     if (nseg < 1) nseg = 1;
-    const int64_t per = (jtiles + nseg - 1) / nseg;  // tiles per segment
+    const int64_t per = jtiles > 0 ? (jtiles + nseg - 1) / nseg : 1;  // tiles per segment
     c.seg_len = (int)(per * c.jt);
-    c.nseg = (int)((jtiles + per - 1) / per);
-    if (c.nseg < 1) c.nseg = 1;
+    c.nseg = jtiles > 0 ? (int)((jtiles + per - 1) / per) : 1;
     *cfg = c;
     return NBODY_OK;
+}
+
+nbody_status choose_cfg(int kernel, int64_t n, int precision, const nbody_opts &o, TileCfg *cfg) {
+    return choose_cfg_ij(kernel, n, n, precision, o, cfg);
 }
 
 size_t partial_bytes(const TileCfg &c, int precision) {
@@ -300,6 +305,50 @@ nbody_status nbody_force_f64(int64_t n, const double *pos64, const float *mass, 
     if ((st = get_workspace(o, f64_scratch_bytes(n, cfg, o.precision), s, &ws))) return st;
     return force_f64_core(n, pos64, mass, eps, acc, pot, o, cfg,
                           f64_scratch_layout(ws, n, cfg, o.precision), nullptr, 0.0, s);
+}
+
+nbody_status nbody_force_ij(int64_t ni, const float *pos_i, const float *eps_i, int64_t nj,
+                            const float *pos_j, const float *mass_j, float eps, double *acc,
+                            double *pot, const nbody_opts *opts, void *stream) {
+    clear_error();
+    nbody_opts o = resolve_opts(opts);
+    if (ni < 0 || ni > INT32_MAX / 2 || nj < 0 || nj > INT32_MAX / 2)
+        return set_error(NBODY_EINVAL, "ni and nj must be in [0, 2^30)");
+    if (ni > 0 && (!pos_i || !acc)) return set_error(NBODY_EINVAL, "pos_i and acc must not be NULL");
+    if (ni > 0 && nj > 0 && (!pos_j || !mass_j))
+        return set_error(NBODY_EINVAL, "pos_j and mass_j must not be NULL");
+    const float e2 = eps * eps;
+    if (!std::isfinite(eps) || !(eps >= 0.0f) || !std::isfinite(e2) || (eps > 0.0f && !(e2 >= FLT_MIN)))
+        return set_error(NBODY_EINVAL, "eps must be finite and >= 0 with eps^2 zero or a normal float");
+    if (o.precision < NBODY_PLAIN || o.precision > NBODY_COMP)
+        return set_error(NBODY_EINVAL, "precision must be NBODY_PLAIN, NBODY_FP64RED or NBODY_COMP");
+    if (misaligned(pos_i) || misaligned(eps_i) || misaligned(pos_j) || misaligned(mass_j) ||
+        misaligned(acc) || misaligned(pot))
+        return set_error(NBODY_EINVAL, "misaligned array argument");
+    if (ni == 0) return NBODY_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    nbody_status st;
+    if (nj == 0) {
+        if ((st = launch_fill_f64(3 * ni, acc, 0.0, s))) return st;
+        return pot ? launch_fill_f64(ni, pot, 0.0, s) : NBODY_OK;
+    }
+    TileCfg cfg;
+    if ((st = choose_cfg_ij(KERNEL_FORCE, ni, nj, o.precision, o, &cfg))) return st;
+    void *ws = nullptr;
+    if ((st = get_workspace(o, partial_bytes(cfg, o.precision), s, &ws))) return st;
+    IJPairArgs a{pos_i, pos_i + ni, pos_i + 2 * ni, eps_i, pos_j, pos_j + nj, pos_j + 2 * nj,
+                 mass_j, (int)ni, (int)nj, cfg.seg_len, e2, ws, cfg.npad};
+    if ((st = launch_pair_ij(cfg, o.precision, pot != nullptr, a, s))) return st;
+    FinalizeArgs fa{ws, cfg.nseg, cfg.npad, (int)ni, nullptr, e2, 0, acc, pot, nullptr, 0.0};
+    return launch_finalize(o.precision, fa, s);
+}
+
+size_t nbody_workspace_size_ij(int64_t ni, int64_t nj, const nbody_opts *opts) {
+    nbody_opts o = resolve_opts(opts);
+    if (ni <= 0 || nj <= 0) return 0;
+    TileCfg c;
+    if (choose_cfg_ij(KERNEL_FORCE, ni, nj, o.precision, o, &c) != NBODY_OK) return 0;
+    return partial_bytes(c, o.precision);
 }
 
 nbody_status nbody_morton_order(int64_t n, const double *pos64, int32_t *perm, void *stream) {

@@ -7,6 +7,30 @@
 
 namespace nbody {
 
+// One softened pair term: separation x_j - x_i, s^2 = |d|^2 + eps^2 as an FMA chain,
+// 1/s from the hardware reciprocal square root (about 1 ulp); a += m d / s^3 and
+// phi -= m / s with m / s rounded on its own.  13 VALU operations and one v_rsq_f32.
+// For j == i the separation is exactly zero, so that pair adds nothing to a and adds
+// -fl(m_i rsq(eps^2)) to phi, which the finalize removes.
+template <bool POT>
+__device__ __forceinline__ void gravity_pair(const float *j, float xi, float yi, float zi,
+                                             float eps2, float (&acc)[4]) {
+    const float dx = j[0] - xi;
+    const float dy = j[1] - yi;
+    const float dz = j[2] - zi;
+    float s2 = __builtin_fmaf(dx, dx, eps2);
+    s2 = __builtin_fmaf(dy, dy, s2);
+    s2 = __builtin_fmaf(dz, dz, s2);
+    const float ri = __builtin_amdgcn_rsqf(s2);
+    const float mri = j[3] * ri;
+    const float ri2 = ri * ri;
+    const float mri3 = mri * ri2;
+    acc[0] = __builtin_fmaf(mri3, dx, acc[0]);
+    acc[1] = __builtin_fmaf(mri3, dy, acc[1]);
+    acc[2] = __builtin_fmaf(mri3, dz, acc[2]);
+    if (POT) acc[3] = acc[3] - mri;
+}
+
 struct Gravity {
     static constexpr int kJWords = 4;  // x, y, z, m
     static constexpr int kOut = 4;     // ax, ay, az, phi
@@ -15,6 +39,8 @@ struct Gravity {
         float x, y, z;
     };
     struct Ctx {};
+    static __device__ __forceinline__ int n_i(const Args &a) { return a.n; }
+    static __device__ __forceinline__ int n_j(const Args &a) { return a.n; }
     static __device__ __forceinline__ Ctx make_ctx(const Args &, int) { return {}; }
     static __device__ __forceinline__ IState load_i(const Args &a, const Ctx &, int i) {
         return {a.x[i], a.y[i], a.z[i]};
@@ -28,28 +54,10 @@ struct Gravity {
     // A massless particle at the origin adds exactly zero.
     static __device__ __forceinline__ void pad_j(float (&r)[4]) { r[0] = r[1] = r[2] = r[3] = 0.0f; }
 
-    // One softened pair term: separation x_j - x_i, s^2 = |d|^2 + eps^2 as an FMA chain,
-    // 1/s from the hardware reciprocal square root (about 1 ulp); a += m d / s^3 and
-    // phi -= m / s with m / s rounded on its own.  13 VALU operations and one
-    // v_rsq_f32.  For j == i the separation is exactly zero, so that pair adds nothing
-    // to a and adds -fl(m_i rsq(eps^2)) to phi, which the finalize removes.
     template <bool POT>
     static __device__ __forceinline__ void pair(const float *j, const IState &i, float eps2,
                                                 float (&acc)[4]) {
-        const float dx = j[0] - i.x;
-        const float dy = j[1] - i.y;
-        const float dz = j[2] - i.z;
-        float s2 = __builtin_fmaf(dx, dx, eps2);
-        s2 = __builtin_fmaf(dy, dy, s2);
-        s2 = __builtin_fmaf(dz, dz, s2);
-        const float ri = __builtin_amdgcn_rsqf(s2);
-        const float mri = j[3] * ri;
-        const float ri2 = ri * ri;
-        const float mri3 = mri * ri2;
-        acc[0] = __builtin_fmaf(mri3, dx, acc[0]);
-        acc[1] = __builtin_fmaf(mri3, dy, acc[1]);
-        acc[2] = __builtin_fmaf(mri3, dz, acc[2]);
-        if (POT) acc[3] = acc[3] - mri;
+        gravity_pair<POT>(j, i.x, i.y, i.z, eps2, acc);
     }
 };
 
@@ -67,6 +75,8 @@ struct GravityTile {
     struct Ctx {
         double cx, cy, cz;
     };
+    static __device__ __forceinline__ int n_i(const Args &a) { return a.n; }
+    static __device__ __forceinline__ int n_j(const Args &a) { return a.n; }
     static __device__ __forceinline__ Ctx make_ctx(const Args &a, int i0) {
         const double *c = a.centres + 3 * (size_t)(i0 / a.itile);
         return {c[0], c[1], c[2]};
@@ -84,7 +94,48 @@ struct GravityTile {
     template <bool POT>
     static __device__ __forceinline__ void pair(const float *j, const IState &i, float eps2,
                                                 float (&acc)[4]) {
-        Gravity::pair<POT>(j, i, eps2, acc);
+        gravity_pair<POT>(j, i.x, i.y, i.z, eps2, acc);
+    }
+};
+
+// Separate i- and j-sets, the paper's library interface (Sec. 3.1): forces on ni
+// i-particles from nj j-particles, with no pair treated as a self pair, and the
+// softening either uniform or given per i-particle (the paper's driver stores eps^2
+// per i).  Padding j-records sit at 1e30 with zero mass: their s^2 overflows to +inf,
+// rsq(+inf) = 0, and every term they add is exactly zero, also when eps = 0.
+struct GravityIJ {
+    static constexpr int kJWords = 4;
+    static constexpr int kOut = 4;
+    using Args = IJPairArgs;
+    struct IState {
+        float x, y, z, e2;
+    };
+    struct Ctx {};
+    static __device__ __forceinline__ int n_i(const Args &a) { return a.ni; }
+    static __device__ __forceinline__ int n_j(const Args &a) { return a.nj; }
+    static __device__ __forceinline__ Ctx make_ctx(const Args &, int) { return {}; }
+    static __device__ __forceinline__ IState load_i(const Args &a, const Ctx &, int i) {
+        float e2 = a.eps2;
+        if (a.ei) {
+            const float e = a.ei[i];
+            e2 = e * e;
+        }
+        return {a.xi[i], a.yi[i], a.zi[i], e2};
+    }
+    static __device__ __forceinline__ void load_j(const Args &a, const Ctx &, int j, float (&r)[4]) {
+        r[0] = a.x[j];
+        r[1] = a.y[j];
+        r[2] = a.z[j];
+        r[3] = a.m[j];
+    }
+    static __device__ __forceinline__ void pad_j(float (&r)[4]) {
+        r[0] = r[1] = r[2] = 1e30f;
+        r[3] = 0.0f;
+    }
+    template <bool POT>
+    static __device__ __forceinline__ void pair(const float *j, const IState &i, float,
+                                                float (&acc)[4]) {
+        gravity_pair<POT>(j, i.x, i.y, i.z, i.e2, acc);
     }
 };
 

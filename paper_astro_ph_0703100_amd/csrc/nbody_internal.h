@@ -66,6 +66,18 @@ struct TilePairArgs {
     int itile;              // particles per i-tile (256 * IPL)
 };
 
+// Arguments of the pair kernel with separate i- and j-sets (FP32 structure of arrays).
+struct IJPairArgs {
+    const float *xi, *yi, *zi;    // i positions [3][ni]
+    const float *ei;              // per-i softening [ni], or nullptr: eps2 for every i
+    const float *x, *y, *z, *m;   // j positions [3][nj] and masses [nj]
+    int ni, nj;
+    int seg_len;
+    float eps2;
+    void *part;
+    int npad;
+};
+
 // One work item of a ragged batch: an i-tile of one system against a j-range of the
 // same system.  Indices are global (into the concatenated arrays).
 struct BatchItem {
@@ -161,6 +173,9 @@ inline bool misaligned(const T *p) {
 bool stream_capturing(hipStream_t s);
 nbody_status get_workspace(const nbody_opts &o, size_t need, hipStream_t s, void **out);
 nbody_status choose_cfg(int kernel, int64_t n, int precision, const nbody_opts &o, TileCfg *cfg);
+// The same for ni i-particles against nj j-particles (nj >= 1).
+nbody_status choose_cfg_ij(int kernel, int64_t ni, int64_t nj, int precision, const nbody_opts &o,
+                           TileCfg *cfg);
 size_t partial_bytes(const TileCfg &c, int precision);
 size_t align_up(size_t v, size_t a);
 nbody_status check_common(int64_t n, const void *pos, const void *mass, float eps,
@@ -199,6 +214,8 @@ const DeviceInfo &device_info();
 nbody_status launch_pair(const TileCfg &cfg, int precision, bool with_pot, const PairArgs &a,
                          hipStream_t s);
 nbody_status launch_finalize(int precision, const FinalizeArgs &a, hipStream_t s);
+nbody_status launch_pair_ij(const TileCfg &cfg, int precision, bool with_pot, const IJPairArgs &a,
+                            hipStream_t s);
 nbody_status launch_centre(int64_t n, const double *pos64, double *centre, double *scratch,
                            hipStream_t s);
 nbody_status launch_convert(int64_t n, const double *pos64, const double *centre, float *pos32,

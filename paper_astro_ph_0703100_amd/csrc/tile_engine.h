@@ -27,7 +27,8 @@
 // An Op provides:
 //   static constexpr int kJWords;            // floats per j-record (multiple of 4)
 //   static constexpr int kOut;               // outputs per i (<= 4)
-//   struct Args;                             // kernel arguments (n, seg_len, eps2, part, npad, ...)
+//   struct Args;                             // kernel arguments (seg_len, eps2, part, npad, ...)
+//   static int n_i(const Args&), n_j(const Args&);  // i- and j-counts of a grid launch
 //   struct IState;                           // per-i registers
 //   struct Ctx;                              // per-block context (e.g. a reference centre)
 //   static Ctx make_ctx(const Args&, int i0);
@@ -217,9 +218,9 @@ template <class Op, int IPL, int JT, int MODE, bool FULL>
 __global__ __launch_bounds__(kTPB) void tile_kernel(typename Op::Args a) {
     __shared__ float4 tile[2][JT * (Op::kJWords / 4)];
     const int i0 = blockIdx.x * (kTPB * IPL);
-    const int ni = min(kTPB * IPL, a.n - i0);
+    const int ni = min(kTPB * IPL, Op::n_i(a) - i0);
     const int j0 = blockIdx.y * a.seg_len;
-    const int nj = max(0, min(a.seg_len, a.n - j0));
+    const int nj = max(0, min(a.seg_len, Op::n_j(a) - j0));
     const size_t plane = (size_t)a.npad;
     constexpr int WO = Op::kOut * words_per_out<MODE>();
     void *out = static_cast<float *>(a.part) + (size_t)blockIdx.y * WO * plane;

@@ -3,7 +3,7 @@
 // File format (written by nbody_tune_save and by tune.py):
 //   {"version": 1, "arch": "gfx950", "entries": [
 //     {"kernel": 0, "precision": 2, "bucket": 17, "ipl": 4, "jtile": 256, "nseg": 16}, ...]}
-// kernel: 0 force, 1 adjoint, 2 batched; precision: 0 plain, 1 FP64-reduced,
+// kernel: 0 force, 1 adjoint, 2 batched, 3 force-jerk; precision: 0 plain, 1 FP64-reduced,
 // 2 compensated; bucket: floor(log2 n) of the particle count (batched: mean system
 // size).  Unknown keys are ignored.
 #include "tuning.h"

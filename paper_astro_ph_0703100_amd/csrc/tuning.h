@@ -6,7 +6,7 @@
 
 namespace nbody {
 
-enum TuneKernel { KERNEL_FORCE = 0, KERNEL_VJP = 1, KERNEL_BATCHED = 2, KERNEL_COUNT = 3 };
+enum TuneKernel { KERNEL_FORCE = 0, KERNEL_VJP = 1, KERNEL_BATCHED = 2, KERNEL_JERK = 3, KERNEL_COUNT = 4 };
 
 struct TuneEntry {
     int ipl;   // i-particles per lane

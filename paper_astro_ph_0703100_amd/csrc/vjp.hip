@@ -27,6 +27,8 @@ struct Adjoint {
         float x, y, z, m, gx, gy, gz, p;
     };
     struct Ctx {};
+    static __device__ __forceinline__ int n_i(const Args &a) { return a.n; }
+    static __device__ __forceinline__ int n_j(const Args &a) { return a.n; }
     static __device__ __forceinline__ Ctx make_ctx(const Args &, int) { return {}; }
     static __device__ __forceinline__ IState load_i(const Args &a, const Ctx &, int i) {
         return {a.x[i], a.y[i], a.z[i], a.m[i], (float)a.gx[i], (float)a.gy[i], (float)a.gz[i],

@@ -70,6 +70,36 @@ def test_force_rejects_invalid_arguments(args, what):
     assert _lib.nbody_last_error() != ""
 
 
+@pytest.mark.parametrize("args,what", [
+    ((-1, FAKE, None, 10, FAKE, FAKE, 0.1, FAKE, None), "negative ni"),
+    ((10, FAKE, None, -1, FAKE, FAKE, 0.1, FAKE, None), "negative nj"),
+    ((10, FAKE, None, 1 << 31, FAKE, FAKE, 0.1, FAKE, None), "nj too large"),
+    ((10, None, None, 10, FAKE, FAKE, 0.1, FAKE, None), "NULL pos_i"),
+    ((10, FAKE, None, 10, None, FAKE, 0.1, FAKE, None), "NULL pos_j"),
+    ((10, FAKE, None, 10, FAKE, None, 0.1, FAKE, None), "NULL mass_j"),
+    ((10, FAKE, None, 10, FAKE, FAKE, 0.1, None, None), "NULL acc"),
+    ((10, FAKE, None, 10, FAKE, FAKE, -1.0, FAKE, None), "eps < 0"),
+    ((10, FAKE, None, 10, FAKE, FAKE, float("nan"), FAKE, None), "eps NaN"),
+    ((10, FAKE, None, 10, FAKE, FAKE, 1e-30, FAKE, None), "eps^2 underflows"),
+    ((10, FAKE, FAKE + 2, 10, FAKE, FAKE, 0.1, FAKE, None), "misaligned eps_i"),
+    ((10, FAKE, None, 10, FAKE, FAKE, 0.1, FAKE, FAKE + 4), "misaligned pot"),
+])
+def test_force_ij_rejects_invalid_arguments(args, what):
+    st = _lib.nbody_force_ij(*args, None, None, check=False)
+    assert st == _lib.NBODY_EINVAL, what
+    assert _lib.nbody_last_error() != ""
+
+
+def test_force_ij_empty_i_set_is_a_no_op():
+    # ni = 0 returns before any device call; eps = 0 is legal for separate sets.
+    assert _lib.nbody_force_ij(0, None, None, 10, FAKE, FAKE, 0.0, None, None, None, None,
+                               check=False) == _lib.NBODY_OK
+    o = _lib.nbody_opts_default()
+    o.ipl = 3
+    assert _lib.nbody_force_ij(10, FAKE, None, 10, FAKE, FAKE, 0.1, FAKE, None, o, None,
+                               check=False) == _lib.NBODY_EINVAL
+
+
 @pytest.mark.parametrize("field,value", [
     ("precision", 3), ("precision", -1), ("self_pot", 2), ("centre", 5),
     ("ipl", 3), ("jtile", 100), ("nseg", -2), ("nseg", 100000),
