@@ -19,10 +19,14 @@ step evaluates):
                  step (persistent work-queue kernel); pairs = sum N_k^2.
   adjoint_16384  N = 16384, 32 KDK steps dt = 1/256 and the reverse pass; step = one
                  loss + gradient (33 force and 33 adjoint evaluations of N^2 pairs).
+  jerk_131072    the N = 131072 sphere; step = one force+jerk+potential evaluation
+                 (the interaction of a fourth-order Hermite integrator) from FP64
+                 positions and velocities.
 
 Roofline: the dominant kernel's duration is taken from HIP events on the launch
-stream (standalone calls), and compared with the VALU issue limit:
-17 slots per gravity pair, 42 per adjoint pair, at 256 CUs x 4 SIMDs x 32 lanes x
+stream (standalone calls), and compared with the VALU issue limit: 17 slots per
+gravity pair (13 FP32 operations and a quarter-rate v_rsq_f32), 31 per
+force-jerk-potential pair, 42 per adjoint pair, at 256 CUs x 4 SIMDs x 32 lanes x
 2.4 GHz.  ``traffic`` comes from the committed rocprofv3 counter summary of the
 same kernel and is null when the kernel sources changed since it was taken.
 
@@ -57,8 +61,10 @@ METRIC = "pair interactions/s at N=131072, compensated vs plain FP32, error vs F
 CUS, SIMDS, LANES, CLOCK_HZ = 256, 4, 32, 2.4e9
 LANE_ISSUE = CUS * SIMDS * LANES * CLOCK_HZ
 RSQ_SLOTS = 4
-SLOTS = {"gravity": 13 + RSQ_SLOTS, "adjoint": 38 + RSQ_SLOTS}
-FLOPS = {"gravity": 20, "adjoint": 45}  # the paper's count per gravity pair (Sec. 1.1)
+SLOTS = {"gravity": 13 + RSQ_SLOTS, "jerk": 27 + RSQ_SLOTS, "adjoint": 38 + RSQ_SLOTS}
+# Flops per pair: the paper's count for gravity (Sec. 1.1); 60 for force, jerk and
+# potential, the count customary for fourth-order Hermite codes; 45 for the adjoint.
+FLOPS = {"gravity": 20, "jerk": 60, "adjoint": 45}
 
 # Kernel sources behind the committed counter summaries (traffic is dropped when they change).
 KERNEL_SOURCES = ["paper_astro_ph_0703100_amd/csrc/tile_engine.h",
@@ -100,7 +106,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="plummer_131072",
                     choices=["plummer_131072", "plummer_2048", "stress_1m", "clusters_2048",
-                             "adjoint_16384"])
+                             "adjoint_16384", "jerk_131072"])
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the FP64 oracle leg (no errors, no CPU rate)")
     ap.add_argument("--cpu-sample", type=int, default=0,
@@ -443,11 +449,84 @@ def bench_adjoint(args, torch, w):
     }
 
 
+def bench_jerk(args, torch, w):
+    from paper_astro_ph_0703100_amd import _lib, api, ics, metrics
+    n = w.n
+    pos, vel, mass = ics.plummer(n, seed=w.seed)
+    m32 = mass.astype(np.float32)
+    eps = float(np.float32(w.eps))
+    dev = torch.device("cuda:0")
+    x = torch.from_numpy(np.ascontiguousarray(pos.T)).to(dev)
+    v = torch.from_numpy(np.ascontiguousarray(vel.T)).to(dev)
+    m = torch.from_numpy(m32).to(dev)
+    p32 = torch.from_numpy(np.ascontiguousarray(pos.T.astype(np.float32))).to(dev)
+    v32 = torch.from_numpy(np.ascontiguousarray(vel.T.astype(np.float32))).to(dev)
+    acc = torch.empty((3, n), dtype=torch.float64, device=dev)
+    jerk = torch.empty((3, n), dtype=torch.float64, device=dev)
+    pot = torch.empty(n, dtype=torch.float64, device=dev)
+    sp = torch.cuda.current_stream().cuda_stream
+    timer = Timer(torch)
+    pairs = float(n) * float(n)
+    res = {}
+    for precision in [s for s in args.modes.split(",") if s]:
+        opts = api.make_opts(precision=precision)
+        step = lambda: _lib.nbody_force_jerk_f64(n, x.data_ptr(), v.data_ptr(), m.data_ptr(), eps,
+                                                 acc.data_ptr(), jerk.data_ptr(), pot.data_ptr(),
+                                                 opts, sp)
+        wall, _ = timer.run(step, args.steps, warmup=args.warmup)
+        host = (acc.cpu().numpy().T.copy(), jerk.cpu().numpy().T.copy(), pot.cpu().numpy().copy())
+        _, kms = timer.run(lambda: _lib.nbody_force_jerk(n, p32.data_ptr(), v32.data_ptr(),
+                                                         m.data_ptr(), eps, acc.data_ptr(),
+                                                         jerk.data_ptr(), pot.data_ptr(), opts, sp),
+                           max(args.steps, 3))
+        res[precision] = {"wall": wall, "kernel_ms": float(np.mean(kms)), "out": host}
+        print("bench: %-8s %d evaluations  %.3f ms each (wall)  jerk kernel %.3f ms"
+              % (precision, args.steps, wall / args.steps * 1e3, np.mean(kms)),
+              file=sys.stderr, flush=True)
+    cpu, errors = None, {}
+    if not args.no_cpu_baseline:
+        import oracle
+        k = 8192 if args.cpu_sample <= 0 else min(n, args.cpu_sample)
+        idx = ics.sample_indices(n, k, seed=w.seed + 1000)
+        t0 = time.perf_counter()
+        ra, rj, rp = oracle.force_jerk(pos, vel, m32.astype(np.float64), eps, idx=idx)
+        ct = time.perf_counter() - t0
+        cpu = {"value": k * float(n) / ct, "unit": "pair-interactions/s",
+               "cores": oracle.threads(), "kind": "oracle",
+               "sample": "force+jerk+potential of %d sampled i-particles from all %d, FP64 "
+                         "(%.1f s)" % (k, n, ct)}
+        for p, r in res.items():
+            a, j, ph = r["out"]
+            e = errors_of(metrics, a[idx], ph[idx], ra, rp)
+            ej = metrics.rel_errors(j[idx], rj)
+            e.update({"jerk_rel_rms": ej["rel_rms"], "jerk_e_max": ej["e_max"],
+                      "jerk_normwise": ej["normwise"]})
+            errors[p] = e
+    head = next(iter(res))
+    r0 = res[head]
+    return {
+        "value": pairs * args.steps / r0["wall"], "ms_per_step": r0["wall"] / args.steps * 1e3,
+        "config": {"workload": w.name, "n": n, "eps": eps, "seed": w.seed, "precision": head,
+                   "step": "one force+jerk+potential evaluation from FP64 positions and "
+                           "velocities (system centres, FP32 pair arithmetic)",
+                   "description": w.description},
+        "roofline": roofline("jerk", pairs, r0["kernel_ms"],
+                             "tile_kernel<GravityJerk> (+ jerk_finalize_kernel)"),
+        "cpu_baseline": cpu,
+        "modes": {p: {"value": pairs * args.steps / r["wall"],
+                      "ms_per_step": r["wall"] / args.steps * 1e3,
+                      "jerk_kernel_ms": r["kernel_ms"],
+                      "roofline_frac": pairs / (r["kernel_ms"] * 1e-3) / peak_pairs("jerk"),
+                      "errors": errors.get(p)} for p, r in res.items()},
+        "gflops_60": pairs * 60 / (r0["kernel_ms"] * 1e-3) / 1e9,
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py: this path runs on one GPU; --gpus %d is not supported "
-              "(the multi-GPU sharding is described in DESIGN.md, not built)" % args.gpus,
+              "(a system would shard by i-range with nbody_force_ij; not built)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
 
@@ -468,7 +547,7 @@ def main():
     w = ics.WORKLOADS[args.workload]
     fn = {"plummer_131072": bench_plummer, "plummer_2048": bench_plummer,
           "stress_1m": bench_stress, "clusters_2048": bench_clusters,
-          "adjoint_16384": bench_adjoint}[w.name]
+          "adjoint_16384": bench_adjoint, "jerk_131072": bench_jerk}[w.name]
     body = fn(args, torch, w)
     line = {
         "metric": METRIC if w.name == "plummer_131072" else "pair interactions/s, " + w.name,

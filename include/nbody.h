@@ -78,7 +78,7 @@ typedef struct nbody_opts {
     int32_t self_pot;   /* 0: phi excludes j == i (default); 1: phi includes -m_i/eps */
     int32_t ipl;        /* i-particles per lane: 1, 2, 4, 8; 0 = tuned/default        */
     int32_t jtile;      /* j-particles per LDS tile: 64, 128, 256, 512; 0 = default   */
-    int32_t nseg;       /* j-segments per i-tile (grid y); 0 = chosen from n          */
+    int32_t nseg;       /* j-segments per i-tile (grid y), <= 1024; 0 = chosen from n */
     void *workspace;    /* device scratch, or NULL for the library's per-device cache */
     size_t workspace_bytes;
 } nbody_opts;
@@ -145,6 +145,36 @@ NBODY_API nbody_status nbody_force_ij(int64_t ni, const float *pos_i, const floa
                                       float eps, double *acc, double *pot,
                                       const nbody_opts *opts, void *stream);
 NBODY_API size_t nbody_workspace_size_ij(int64_t ni, int64_t nj, const nbody_opts *opts);
+
+/* ------------------------------------------------------------------------------
+ * Force, jerk and potential in one pass: the force-jerk-potential pipeline of the
+ * paper's Appendix A, the interaction a fourth-order Hermite integrator needs
+ * (Sec. 5.1).  With d = x_j - x_i, w = v_j - v_i, s^2 = |d|^2 + eps^2:
+ *   a_i = sum m_j d / s^3,  jerk_i = sum m_j (w / s^3 - 3 (d.w) d / s^5),
+ *   phi_i = -sum m_j / s,
+ * all i against all j of one system, j == i excluded as in nbody_force (self_pot = 1
+ * keeps -m_i/eps in phi).
+ *   n      particles, 0 <= n < 2^30
+ *   pos    float [3][n], vel float [3][n], mass float [n] (read)
+ *   eps    softening length (> 0, eps^2 a normal float)
+ *   acc    double [3][n], jerk double [3][n] (written); pot double [n] or NULL
+ *   opts   precision, self_pot, ipl, jtile, nseg, workspace; NULL = defaults
+ * Scratch: nbody_workspace_size_jerk bytes (covers both entry points), from
+ * opts->workspace or the per-device cache.  Outputs must not alias inputs.
+ * ---------------------------------------------------------------------------- */
+NBODY_API nbody_status nbody_force_jerk(int64_t n, const float *pos, const float *vel,
+                                        const float *mass, float eps, double *acc, double *jerk,
+                                        double *pot, const nbody_opts *opts, void *stream);
+/* As nbody_force_jerk with FP64 state pos64, vel64 double [3][n]: the pair arithmetic
+ * is FP32 on positions relative to the FP64 mean position and velocities relative to
+ * the FP64 mean velocity (opts->centre = NBODY_CENTRE_SYSTEM, default) or on the
+ * plain FP32 roundings (NBODY_CENTRE_NONE); NBODY_CENTRE_TILE gives
+ * NBODY_EUNSUPPORTED. */
+NBODY_API nbody_status nbody_force_jerk_f64(int64_t n, const double *pos64, const double *vel64,
+                                            const float *mass, float eps, double *acc,
+                                            double *jerk, double *pot, const nbody_opts *opts,
+                                            void *stream);
+NBODY_API size_t nbody_workspace_size_jerk(int64_t n, const nbody_opts *opts);
 
 /* Morton (Z-order) permutation of FP64 positions pos64 double [3][n]: perm int32 [n]
  * (device, written) lists the particle indices in order along the Z-curve of the

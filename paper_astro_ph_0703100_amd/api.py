@@ -105,6 +105,29 @@ def force_ij(pos_i: torch.Tensor, pos_j: torch.Tensor, mass_j: torch.Tensor, eps
     return acc, pot
 
 
+def force_jerk(pos: torch.Tensor, vel: torch.Tensor, mass: torch.Tensor, eps: float,
+               precision: str = "comp", with_pot: bool = True, out=None, **kw):
+    """``(acc, jerk, pot)``: accelerations and jerks ``[3, n]`` and potentials ``[n]``
+    (float64) from float32 (``[3, n]``) or float64 state; float64 state is taken relative
+    to its mean position and velocity (``centre="system"``) or just rounded
+    (``centre="none"``)."""
+    f64 = pos.dtype == torch.float64
+    n = _check_pos(pos, torch.float64 if f64 else torch.float32)
+    if _check_pos(vel, pos.dtype, "vel") != n:
+        raise ValueError("vel must have the shape of pos")
+    _check_vec(mass, n, torch.float32, "mass")
+    dev = pos.device
+    acc, jerk, pot = out if out is not None else (
+        torch.empty((3, n), dtype=torch.float64, device=dev),
+        torch.empty((3, n), dtype=torch.float64, device=dev),
+        torch.empty(n, dtype=torch.float64, device=dev) if with_pot else None)
+    opts = make_opts(precision=precision, **kw)
+    fn = _lib.nbody_force_jerk_f64 if f64 else _lib.nbody_force_jerk
+    fn(n, pos.data_ptr(), vel.data_ptr(), mass.data_ptr(), float(eps), acc.data_ptr(),
+       jerk.data_ptr(), pot.data_ptr() if pot is not None else None, opts, stream_ptr())
+    return acc, jerk, pot
+
+
 def morton_order(pos64: torch.Tensor) -> torch.Tensor:
     """int32 permutation ``[n]`` ordering the particles along the Z-curve."""
     n = _check_pos(pos64, torch.float64, "pos64")

@@ -1,0 +1,126 @@
+// Force, jerk and potential in one pass: the force-jerk-potential pipeline of the
+// paper's Appendix A (the interaction of a fourth-order Hermite integrator, Sec. 5.1)
+// on the tile engine.  With d = x_j - x_i, w = v_j - v_i and s^2 = |d|^2 + eps^2:
+//   a_i    +=  m_j d / s^3
+//   jerk_i +=  m_j (w - 3 (d.w / s^2) d) / s^3
+//   phi_i  -=  m_j / s
+// j-records are 8 floats (x, y, z, m, vx, vy, vz, 0: two 16-byte LDS reads per j);
+// i-records hold position and velocity.  27 FP32 VALU operations and one v_rsq_f32
+// per pair.
+#include "tile_engine.h"
+
+namespace nbody {
+namespace {
+
+struct GravityJerk {
+    static constexpr int kJWords = 8;
+    static constexpr int kOut = 7;  // ax, ay, az, jx, jy, jz, phi
+    using Args = JerkArgs;
+    struct IState {
+        float x, y, z, vx, vy, vz;
+    };
+    struct Ctx {};
+    static __device__ __forceinline__ int n_i(const Args &a) { return a.n; }
+    static __device__ __forceinline__ int n_j(const Args &a) { return a.n; }
+    static __device__ __forceinline__ Ctx make_ctx(const Args &, int) { return {}; }
+    static __device__ __forceinline__ IState load_i(const Args &a, const Ctx &, int i) {
+        return {a.x[i], a.y[i], a.z[i], a.vx[i], a.vy[i], a.vz[i]};
+    }
+    static __device__ __forceinline__ void load_j(const Args &a, const Ctx &, int j, float (&r)[8]) {
+        r[0] = a.x[j];
+        r[1] = a.y[j];
+        r[2] = a.z[j];
+        r[3] = a.m[j];
+        r[4] = a.vx[j];
+        r[5] = a.vy[j];
+        r[6] = a.vz[j];
+        r[7] = 0.0f;
+    }
+    // A massless particle at rest at the origin: every term carries m = 0.
+    static __device__ __forceinline__ void pad_j(float (&r)[8]) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) r[c] = 0.0f;
+    }
+    // For j == i both d and w are exactly zero, so the pair adds nothing to a and the
+    // jerk and -fl(m_i rsq(eps^2)) to phi, which the finalize removes.
+    template <bool POT>
+    static __device__ __forceinline__ void pair(const float *j, const IState &i, float eps2,
+                                                float (&acc)[7]) {
+        const float dx = j[0] - i.x;
+        const float dy = j[1] - i.y;
+        const float dz = j[2] - i.z;
+        const float wx = j[4] - i.vx;
+        const float wy = j[5] - i.vy;
+        const float wz = j[6] - i.vz;
+        float s2 = __builtin_fmaf(dx, dx, eps2);
+        s2 = __builtin_fmaf(dy, dy, s2);
+        s2 = __builtin_fmaf(dz, dz, s2);
+        const float ri = __builtin_amdgcn_rsqf(s2);
+        const float ri2 = ri * ri;
+        const float mri = j[3] * ri;
+        const float mri3 = mri * ri2;
+        float dw = dx * wx;
+        dw = __builtin_fmaf(dy, wy, dw);
+        dw = __builtin_fmaf(dz, wz, dw);
+        const float al = (dw * ri2) * 3.0f;
+        const float tx = __builtin_fmaf(-al, dx, wx);
+        const float ty = __builtin_fmaf(-al, dy, wy);
+        const float tz = __builtin_fmaf(-al, dz, wz);
+        acc[0] = __builtin_fmaf(mri3, dx, acc[0]);
+        acc[1] = __builtin_fmaf(mri3, dy, acc[1]);
+        acc[2] = __builtin_fmaf(mri3, dz, acc[2]);
+        acc[3] = __builtin_fmaf(mri3, tx, acc[3]);
+        acc[4] = __builtin_fmaf(mri3, ty, acc[4]);
+        acc[5] = __builtin_fmaf(mri3, tz, acc[5]);
+        if (POT) acc[6] = acc[6] - mri;
+    }
+};
+
+template <int MODE>
+__global__ __launch_bounds__(256) void jerk_finalize_kernel(JerkFinalizeArgs a) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    double r[7];
+    engine::sum_partials<7, MODE>(a.part, a.nseg, (size_t)a.npad, i, r);
+    if (a.exclude_self) {
+        const float self = a.m[i] * __builtin_amdgcn_rsqf(a.eps2);
+        if constexpr (MODE == NBODY_PLAIN)
+            r[6] = (double)((float)r[6] + self);
+        else
+            r[6] += (double)self;
+    }
+    const size_t n = (size_t)a.n;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        a.acc[c * n + i] = r[c];
+        a.jerk[c * n + i] = r[3 + c];
+    }
+    if (a.pot) a.pot[i] = r[6];
+}
+
+}  // namespace
+
+nbody_status launch_jerk(const TileCfg &cfg, int precision, bool with_pot, const JerkArgs &a,
+                         hipStream_t s) {
+    auto fn = engine::pick_tile<GravityJerk>(cfg.ipl, cfg.jt, precision, with_pot);
+    if (!fn) return set_error(NBODY_EUNSUPPORTED, "no jerk kernel for this ipl/jtile/precision");
+    if (cfg.itiles <= 0 || cfg.nseg <= 0) return NBODY_OK;
+    hipLaunchKernelGGL(fn, dim3(cfg.itiles, cfg.nseg), dim3(kTPB), 0, s, a);
+    NBODY_HIP_CHECK(hipGetLastError());
+    return NBODY_OK;
+}
+
+nbody_status launch_jerk_finalize(int precision, const JerkFinalizeArgs &a, hipStream_t s) {
+    if (a.n <= 0) return NBODY_OK;
+    const dim3 grid((a.n + 255) / 256);
+    switch (precision) {
+        case NBODY_PLAIN: hipLaunchKernelGGL(jerk_finalize_kernel<NBODY_PLAIN>, grid, dim3(256), 0, s, a); break;
+        case NBODY_FP64RED: hipLaunchKernelGGL(jerk_finalize_kernel<NBODY_FP64RED>, grid, dim3(256), 0, s, a); break;
+        case NBODY_COMP: hipLaunchKernelGGL(jerk_finalize_kernel<NBODY_COMP>, grid, dim3(256), 0, s, a); break;
+        default: return set_error(NBODY_EINVAL, "unknown precision mode");
+    }
+    NBODY_HIP_CHECK(hipGetLastError());
+    return NBODY_OK;
+}
+
+}  // namespace nbody

@@ -24,7 +24,7 @@ namespace nbody {
 // a compute unit.
 constexpr int kTPB = 256;
 // Largest number of j-segments a launch may split the j range into.
-constexpr int kMaxSeg = 128;
+constexpr int kMaxSeg = 1024;
 // j's summed in plain FP32 between two compensation / FP64 steps.
 constexpr int kBlockJ = 32;
 
@@ -76,6 +76,28 @@ struct IJPairArgs {
     float eps2;
     void *part;
     int npad;
+};
+
+// Arguments of the force-jerk-potential kernel (FP32 structure of arrays).
+struct JerkArgs {
+    const float *x, *y, *z, *m;   // positions [3][n] and masses [n]
+    const float *vx, *vy, *vz;    // velocities [3][n]
+    int n;
+    int seg_len;
+    float eps2;
+    void *part;                   // partial sums [nseg][7 * words][npad]
+    int npad;
+};
+
+struct JerkFinalizeArgs {
+    const void *part;
+    int nseg, npad, n;
+    const float *m;
+    float eps2;
+    int exclude_self;
+    double *acc;   // [3][n]
+    double *jerk;  // [3][n]
+    double *pot;   // [n] or nullptr
 };
 
 // One work item of a ragged batch: an i-tile of one system against a j-range of the
@@ -252,6 +274,10 @@ nbody_status launch_system_centres(int nsys, const int64_t *offsets, int64_t tot
                                    const double *pos64, double *centre, hipStream_t s);
 nbody_status launch_batched_convert(int64_t total, const double *pos64, const int32_t *sys_of,
                                     const double *centre, float *pos32, hipStream_t s);
+// Force-jerk-potential kernel and its FP64 finalize (jerk.hip).
+nbody_status launch_jerk(const TileCfg &cfg, int precision, bool with_pot, const JerkArgs &a,
+                         hipStream_t s);
+nbody_status launch_jerk_finalize(int precision, const JerkFinalizeArgs &a, hipStream_t s);
 // Adjoint pair kernel and its FP64 finalize (vjp.hip).
 nbody_status launch_vjp(const TileCfg &cfg, int precision, const VjpArgs &a, bool with_mass,
                         hipStream_t s);

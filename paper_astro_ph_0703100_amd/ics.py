@@ -248,6 +248,10 @@ WORKLOADS = {
         description="N=131072 Plummer (a=1, M=1, equal masses, truncated at 20) with "
                     "distribution-function velocities, eps=0.4/N^(1/3); force+potential and "
                     "KDK leapfrog steps dt=1/256"),
+    "jerk_131072": Workload(
+        "jerk_131072", 131072, plummer_131072_eps(131072), 2,
+        description="N=131072 Plummer as plummer_131072 (same seed and eps); one "
+                    "force+jerk+potential evaluation from FP64 positions and velocities"),
     "stress_1m": Workload(
         "stress_1m", 1 << 20, 1e-4, 3,
         description="N=2^20 halo + 10%-mass core of scale 1e-3 at (1000,0,0), log-uniform "

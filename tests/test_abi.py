@@ -90,6 +90,30 @@ def test_force_ij_rejects_invalid_arguments(args, what):
     assert _lib.nbody_last_error() != ""
 
 
+@pytest.mark.parametrize("args,what", [
+    ((-1, FAKE, FAKE, FAKE, 0.1, FAKE, FAKE, None), "negative n"),
+    ((10, FAKE, None, FAKE, 0.1, FAKE, FAKE, None), "NULL vel"),
+    ((10, FAKE, FAKE, FAKE, 0.1, FAKE, None, None), "NULL jerk"),
+    ((10, FAKE, FAKE, None, 0.1, FAKE, FAKE, None), "NULL mass"),
+    ((10, FAKE, FAKE, FAKE, 0.0, FAKE, FAKE, None), "eps = 0"),
+    ((10, FAKE, FAKE + 2, FAKE, 0.1, FAKE, FAKE, None), "misaligned vel"),
+    ((10, FAKE, FAKE, FAKE, 0.1, FAKE, FAKE + 4, None), "misaligned jerk"),
+])
+@pytest.mark.parametrize("entry", ["nbody_force_jerk", "nbody_force_jerk_f64"])
+def test_force_jerk_rejects_invalid_arguments(entry, args, what):
+    st = getattr(_lib, entry)(*args, None, None, check=False)
+    assert st == _lib.NBODY_EINVAL, what
+
+
+def test_force_jerk_options():
+    o = _lib.nbody_opts_default()
+    o.centre = _lib.NBODY_CENTRE_TILE
+    assert _lib.nbody_force_jerk_f64(10, FAKE, FAKE, FAKE, 0.1, FAKE, FAKE, None, o, None,
+                                     check=False) == _lib.NBODY_EUNSUPPORTED
+    assert _lib.nbody_force_jerk(0, None, None, None, 0.1, None, None, None, None, None,
+                                 check=False) == _lib.NBODY_OK
+
+
 def test_force_ij_empty_i_set_is_a_no_op():
     # ni = 0 returns before any device call; eps = 0 is legal for separate sets.
     assert _lib.nbody_force_ij(0, None, None, 10, FAKE, FAKE, 0.0, None, None, None, None,
