@@ -21,6 +21,9 @@ Parity status of each function (what pins it; the pins are in tests/test_oracle.
   rollout             : time reversibility, second-order energy error, two-body
       circular orbit.
   rollout_loss_grad   : central finite differences of the rollout loss.
+  hermite             : two-body circular orbit with fourth-order phase error,
+      fourth-order energy error, agreement with the (pinned) leapfrog at a much
+      smaller step, exact free motion.
   fp32_replay         : the paper's Table 2 magnitudes (order of magnitude only).
 """
 from __future__ import annotations
@@ -62,6 +65,9 @@ def _load():
             build()
             lib = ctypes.CDLL(_LIB)
             lib.oracle_force.argtypes = [_I64, _D, _D, _I64, _D, _L, ctypes.c_double, _D, _D]
+            lib.oracle_hermite.argtypes = [_I64, _D, _D, _D, ctypes.c_double, ctypes.c_double,
+                                           _I64, _D, _D]
+            lib.oracle_set_threads.argtypes = [ctypes.c_int]
             lib.oracle_force_epsi.argtypes = [_I64, _D, _D, _I64, _D, _D, _D, _D]
             lib.oracle_force_jerk.argtypes = [_I64, _D, _D, _D, _I64, _D, _D, _L, ctypes.c_double,
                                               _D, _D, _D]
@@ -96,6 +102,14 @@ def _f64(a, shape=None):
 def threads() -> int:
     """OpenMP threads the oracle runs with (``OMP_NUM_THREADS`` or all host threads)."""
     return int(_load().oracle_threads())
+
+
+def set_threads(n: int) -> int:
+    """Run the oracle on ``n`` OpenMP threads from now on; returns the previous count."""
+    lib = _load()
+    old = int(lib.oracle_threads())
+    lib.oracle_set_threads(int(n))
+    return old
 
 
 def force_all(x, m, eps):
@@ -195,6 +209,18 @@ def rollout(x0, v0, m, eps, dt, nsteps, keep_trajectory=False):
     _load().oracle_rollout(n, _p(x), _p(v), _p(m), float(eps), float(dt), int(nsteps),
                            _p(traj), _p(acc))
     return x, v, acc, traj
+
+
+def hermite(x0, v0, m, eps, dt, nsteps):
+    """Fourth-order Hermite (shared step): returns (x_T, v_T, a_T, jerk_T)."""
+    x = _f64(x0).copy()
+    n = x.shape[0]
+    v = _f64(v0, (n, 3)).copy()
+    m = _f64(m, (n,))
+    acc, jerk = np.empty((n, 3)), np.empty((n, 3))
+    _load().oracle_hermite(n, _p(x), _p(v), _p(m), float(eps), float(dt), int(nsteps), _p(acc),
+                           _p(jerk))
+    return x, v, acc, jerk
 
 
 def rollout_loss_grad(x0, v0, m, eps, dt, nsteps, target):

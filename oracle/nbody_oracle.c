@@ -371,10 +371,57 @@ OR_EXPORT void oracle_fp32_replay(int64_t n, const float *x, const float *m, flo
     }
 }
 
+/* ------------------------------------------------------------------------- */
+/* Fourth-order Hermite integration with a shared step (the integrator the     */
+/* paper's force-jerk interaction serves, Sec. 5.1), in the predictor-         */
+/* evaluate-corrector form of Makino & Aarseth (1992):                          */
+/*   x_p = x + v dt + a dt^2/2 + j dt^3/6,   v_p = v + a dt + j dt^2/2          */
+/*   (a1, j1) = F(x_p, v_p)                                                     */
+/*   v' = v + (a + a1) dt/2 + (j - j1) dt^2/12                                  */
+/*   x' = x + (v + v') dt/2 + (a - a1) dt^2/12                                  */
+/* and (a, j) <- (a1, j1) for the next step.  (a, j) at the start are computed  */
+/* from (x, v).  x, v are updated in place; acc_out, jerk_out (may be NULL)     */
+/* receive the last (a1, j1).                                                   */
+/* ------------------------------------------------------------------------- */
+OR_EXPORT void oracle_hermite(int64_t n, double *x, double *v, const double *m, double eps,
+                              double dt, int64_t nsteps, double *acc_out, double *jerk_out)
+{
+    const size_t n3 = 3 * (size_t)n;
+    const size_t bytes = sizeof(double) * (n3 ? n3 : 1);
+    double *a = (double *)malloc(bytes), *j = (double *)malloc(bytes);
+    double *a1 = (double *)malloc(bytes), *j1 = (double *)malloc(bytes);
+    double *xp = (double *)malloc(bytes), *vp = (double *)malloc(bytes);
+    int64_t *self = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i)
+        self[i] = i;
+    oracle_force_jerk(n, x, v, m, n, x, v, self, eps, a, j, NULL);
+    for (int64_t t = 0; t < nsteps; ++t) {
+        for (size_t q = 0; q < n3; ++q) {
+            xp[q] = x[q] + v[q] * dt + a[q] * dt * dt / 2.0 + j[q] * dt * dt * dt / 6.0;
+            vp[q] = v[q] + a[q] * dt + j[q] * dt * dt / 2.0;
+        }
+        oracle_force_jerk(n, xp, vp, m, n, xp, vp, self, eps, a1, j1, NULL);
+        for (size_t q = 0; q < n3; ++q) {
+            const double vn = v[q] + (a[q] + a1[q]) * dt / 2.0 + (j[q] - j1[q]) * dt * dt / 12.0;
+            x[q] = x[q] + (v[q] + vn) * dt / 2.0 + (a[q] - a1[q]) * dt * dt / 12.0;
+            v[q] = vn;
+            a[q] = a1[q];
+            j[q] = j1[q];
+        }
+    }
+    if (acc_out)
+        memcpy(acc_out, a, n3 * sizeof(double));
+    if (jerk_out)
+        memcpy(jerk_out, j, n3 * sizeof(double));
+    free(a); free(j); free(a1); free(j1); free(xp); free(vp); free(self);
+}
+
 /* Number of OpenMP threads the oracle uses (1 without OpenMP). */
 #ifdef _OPENMP
 #include <omp.h>
 OR_EXPORT int oracle_threads(void) { return omp_get_max_threads(); }
+OR_EXPORT void oracle_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
 #else
 OR_EXPORT int oracle_threads(void) { return 1; }
+OR_EXPORT void oracle_set_threads(int n) { (void)n; }
 #endif

@@ -396,6 +396,58 @@ def test_two_body_circular_orbit():
     assert np.abs(sep - 1.0).max() < 1e-4
 
 
+def test_hermite_circular_orbit_fourth_order():
+    # The two-body circular orbit above, integrated with the fourth-order Hermite scheme:
+    # the position error after one period falls by about 2^4 when dt halves, and is far
+    # below the leapfrog's at the same step.
+    eps = 0.01
+    om = (1 + eps * eps) ** -0.75
+    x0 = np.array([[0.5, 0, 0], [-0.5, 0, 0]])
+    v0 = np.array([[0, 0.5 * om, 0], [0, -0.5 * om, 0]])
+    m = np.array([0.5, 0.5])
+    period = 2 * math.pi / om
+    errs = []
+    for nsteps in (100, 200):
+        x, v, _, _ = oracle.hermite(x0, v0, m, eps, period / nsteps, nsteps)
+        errs.append(np.abs(x - x0).max())
+    assert 11 < errs[0] / errs[1] < 22, errs
+    xl, _, _, _ = oracle.rollout(x0, v0, m, eps, period / 200, 200)
+    assert errs[1] < 0.01 * np.abs(xl - x0).max()
+    # One step against the exact rotation by omega dt: a fourth-order scheme has local
+    # errors O(dt^5) in both position and velocity (ratio about 32 when dt halves).
+    loc = []
+    for dt in (0.1, 0.05):
+        x, v, _, _ = oracle.hermite(x0, v0, m, eps, dt, 1)
+        c, s_ = math.cos(om * dt), math.sin(om * dt)
+        xe = np.array([[0.5 * c, 0.5 * s_, 0], [-0.5 * c, -0.5 * s_, 0]])
+        ve = np.array([[-0.5 * om * s_, 0.5 * om * c, 0], [0.5 * om * s_, -0.5 * om * c, 0]])
+        loc.append((np.abs(x - xe).max(), np.abs(v - ve).max()))
+    assert 24 < loc[0][0] / loc[1][0] < 40, loc
+    assert 24 < loc[0][1] / loc[1][1] < 40, loc
+
+
+def test_hermite_energy_order_and_leapfrog_limit():
+    x0, v0, m = ics.plummer(48, seed=43)
+    eps, T = 0.05, 0.25
+
+    def energy_err(nsteps):
+        x, v, _, _ = oracle.hermite(x0, v0, m, eps, T / nsteps, nsteps)
+        return abs(oracle.energy(x, v, m, eps) - oracle.energy(x0, v0, m, eps))
+
+    e1, e2 = energy_err(32), energy_err(64)
+    assert 8 < e1 / e2 < 40, (e1, e2)
+    # Both integrators converge to the same trajectory.
+    xh, vh, _, _ = oracle.hermite(x0, v0, m, eps, T / 256, 256)
+    xl, vl, _, _ = oracle.rollout(x0, v0, m, eps, T / 4096, 4096)
+    assert np.abs(xh - xl).max() < 1e-7
+    assert np.abs(vh - vl).max() < 1e-6
+    # Free motion is exact: one particle moves in a straight line.
+    x, v, a, j = oracle.hermite(np.array([[1.0, 2.0, 3.0]]), np.array([[0.5, -0.25, 2.0]]),
+                                np.array([1.0]), 0.1, 0.125, 8)
+    np.testing.assert_array_equal(x, [[1.5, 1.75, 5.0]])
+    assert np.all(a == 0) and np.all(j == 0)
+
+
 def test_leapfrog_time_reversibility_and_energy_order():
     x0, v0, m = ics.plummer(64, seed=41)
     eps = 0.05
