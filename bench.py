@@ -19,9 +19,9 @@ step evaluates):
                  step (persistent work-queue kernel); pairs = sum N_k^2.
   adjoint_16384  N = 16384, 32 KDK steps dt = 1/256 and the reverse pass; step = one
                  loss + gradient (33 force and 33 adjoint evaluations of N^2 pairs).
-  jerk_131072    the N = 131072 sphere; step = one force+jerk+potential evaluation
-                 (the interaction of a fourth-order Hermite integrator) from FP64
-                 positions and velocities.
+  jerk_131072    the N = 131072 sphere; step = one graph-replayed fourth-order Hermite
+                 step (dt = 1/256): FP64 predictor, one N^2 force+jerk evaluation from
+                 the predicted state, FP64 corrector.
 
 Roofline: the dominant kernel's duration is taken from HIP events on the launch
 stream (standalone calls), and compared with the VALU issue limit: 17 slots per
@@ -66,11 +66,13 @@ SLOTS = {"gravity": 13 + RSQ_SLOTS, "jerk": 27 + RSQ_SLOTS, "adjoint": 38 + RSQ_
 # potential, the count customary for fourth-order Hermite codes; 45 for the adjoint.
 FLOPS = {"gravity": 20, "jerk": 60, "adjoint": 45}
 
-# Kernel sources behind the committed counter summaries (traffic is dropped when they change).
+# Kernel sources behind the committed counter summaries, and the tuning file whose
+# force-kernel entries for N = 131072 (size bucket 17) pick the launch shape (traffic is
+# dropped when either changes).
 KERNEL_SOURCES = ["paper_astro_ph_0703100_amd/csrc/tile_engine.h",
                   "paper_astro_ph_0703100_amd/csrc/gravity.h",
-                  "paper_astro_ph_0703100_amd/csrc/force.hip",
-                  "paper_astro_ph_0703100_amd/tuning_gfx950.json"]
+                  "paper_astro_ph_0703100_amd/csrc/force.hip"]
+TUNING_FILE = "paper_astro_ph_0703100_amd/tuning_gfx950.json"
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "pair_kernel_plummer_131072.md")
 
 
@@ -83,6 +85,11 @@ def sources_hash() -> str:
     for rel in KERNEL_SOURCES:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
+    with open(os.path.join(ROOT, TUNING_FILE)) as f:
+        force = [e for e in json.load(f)["entries"]
+                 if e.get("kernel") == 0 and e.get("bucket") == 17]
+    h.update(json.dumps(sorted(force, key=lambda e: (e["precision"], e["bucket"])),
+                        sort_keys=True).encode())
     return h.hexdigest()[:16]
 
 
@@ -141,6 +148,20 @@ class Timer:
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         return wall, [a.elapsed_time(b) for a, b in ev]
+
+
+def one_thread(cpu, call, pairs, what):
+    """Add the oracle's single-thread rate on a smaller piece of the same work to ``cpu``."""
+    import oracle
+    old = oracle.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        call()
+        ct = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(old)
+    cpu["value_1_thread"] = pairs / ct
+    cpu["sample_1_thread"] = "%s (%.2f s)" % (what, ct)
 
 
 def errors_of(metrics, acc, pot, ra, rp):
@@ -217,6 +238,9 @@ def bench_plummer(args, torch, w):
                "cores": oracle.threads(), "kind": "oracle",
                "sample": "force+potential of %d i-particles from all %d particles of the same "
                          "sphere at the initial positions, FP64 (%.1f s)" % (k, n, ct)}
+        i1 = ics.sample_indices(n, 512, seed=w.seed + 2000)
+        one_thread(cpu, lambda: oracle.force_sampled(pos, m32.astype(np.float64), eps, i1),
+                   512.0 * n, "force+potential of 512 sampled i-particles from all %d" % n)
         for p, r in res.items():
             errors[p] = errors_of(metrics, r["acc"][idx], r["pot"][idx], ra, rp)
     head = next(iter(res))
@@ -283,6 +307,8 @@ def bench_stress(args, torch, w):
                "cores": oracle.threads(), "kind": "oracle",
                "sample": "%d stratified i-particles (half core, half halo) from all %d, FP64 "
                          "(%.1f s)" % (idx.size, n, ct)}
+        one_thread(cpu, lambda: oracle.force_sampled(pos, m32.astype(np.float64), eps, idx[::16]),
+                   float(idx[::16].size) * n, "%d of those i-particles" % idx[::16].size)
         for p, out in res.items():
             for centre, r in out.items():
                 errors["%s/%s" % (p, centre)] = errors_of(metrics, r["acc"][idx], r["pot"][idx],
@@ -355,6 +381,11 @@ def bench_clusters(args, torch, w):
         cpu = {"value": cpairs / ct, "unit": "pair-interactions/s", "cores": oracle.threads(),
                "kind": "oracle", "sample": "%d of the clusters (incl. smallest and largest), "
                                            "%.3g pairs, FP64 (%.1f s)" % (len(pick), cpairs, ct)}
+        k1 = pick[0]
+        sl = slice(b.offsets[k1], b.offsets[k1 + 1])
+        one_thread(cpu, lambda: oracle.force_all(b.pos[sl], m32[sl].astype(np.float64),
+                                                 float(np.float32(w.eps))),
+                   float(b.sizes[k1]) ** 2, "cluster %d (N = %d)" % (k1, b.sizes[k1]))
         for p, r in res.items():
             sel = np.concatenate([np.arange(b.offsets[k], b.offsets[k + 1]) for k in pick])
             ref = np.concatenate([refs[k] for k in pick])
@@ -427,6 +458,9 @@ def bench_adjoint(args, torch, w):
                "kind": "oracle", "sample": "the whole loss and gradient (%d forward + %d adjoint "
                                            "evaluations of %d^2 pairs), FP64 (%.1f s)"
                                            % (w.steps + 1, w.steps + 1, n, ct)}
+        g1 = np.random.default_rng(w.seed + 2000).standard_normal((4096, 3))
+        one_thread(cpu, lambda: oracle.vjp(x0[:4096], m64[:4096], eps, g1), 4096.0 ** 2,
+                   "one adjoint evaluation on the first 4096 particles")
         loss, gxg, gvg, gmg = state["g"]
         errors["comp"] = {
             "loss_rel": abs(loss - lo) / abs(lo),
@@ -467,20 +501,30 @@ def bench_jerk(args, torch, w):
     sp = torch.cuda.current_stream().cuda_stream
     timer = Timer(torch)
     pairs = float(n) * float(n)
+    dt = w.dt or 1.0 / 256
     res = {}
     for precision in [s for s in args.modes.split(",") if s]:
         opts = api.make_opts(precision=precision)
-        step = lambda: _lib.nbody_force_jerk_f64(n, x.data_ptr(), v.data_ptr(), m.data_ptr(), eps,
-                                                 acc.data_ptr(), jerk.data_ptr(), pot.data_ptr(),
-                                                 opts, sp)
-        wall, _ = timer.run(step, args.steps, warmup=args.warmup)
+        xs, vs = x.clone(), v.clone()
+        ha, hj = api.hermite(xs, vs, m, eps, dt, 0, precision=precision)
+        g = api.HermiteGraph(xs, vs, m, eps, dt, 1, ha, hj, precision=precision)
+        for _ in range(args.warmup):
+            g.launch()
+        torch.cuda.synchronize()
+        xs.copy_(x)
+        vs.copy_(v)
+        api.hermite(xs, vs, m, eps, dt, 0, acc=ha, jerk=hj, precision=precision)
+        wall, _ = timer.run(g.launch, args.steps, warmup=0)
+        g.close()
+        _lib.nbody_force_jerk_f64(n, x.data_ptr(), v.data_ptr(), m.data_ptr(), eps, acc.data_ptr(),
+                                  jerk.data_ptr(), pot.data_ptr(), opts, sp)
         host = (acc.cpu().numpy().T.copy(), jerk.cpu().numpy().T.copy(), pot.cpu().numpy().copy())
         _, kms = timer.run(lambda: _lib.nbody_force_jerk(n, p32.data_ptr(), v32.data_ptr(),
                                                          m.data_ptr(), eps, acc.data_ptr(),
                                                          jerk.data_ptr(), pot.data_ptr(), opts, sp),
                            max(args.steps, 3))
         res[precision] = {"wall": wall, "kernel_ms": float(np.mean(kms)), "out": host}
-        print("bench: %-8s %d evaluations  %.3f ms each (wall)  jerk kernel %.3f ms"
+        print("bench: %-8s %d Hermite steps  %.3f ms/step (wall)  jerk kernel %.3f ms"
               % (precision, args.steps, wall / args.steps * 1e3, np.mean(kms)),
               file=sys.stderr, flush=True)
     cpu, errors = None, {}
@@ -495,6 +539,9 @@ def bench_jerk(args, torch, w):
                "cores": oracle.threads(), "kind": "oracle",
                "sample": "force+jerk+potential of %d sampled i-particles from all %d, FP64 "
                          "(%.1f s)" % (k, n, ct)}
+        i1 = idx[::16]
+        one_thread(cpu, lambda: oracle.force_jerk(pos, vel, m32.astype(np.float64), eps, idx=i1),
+                   float(i1.size) * n, "%d of those i-particles" % i1.size)
         for p, r in res.items():
             a, j, ph = r["out"]
             e = errors_of(metrics, a[idx], ph[idx], ra, rp)
@@ -506,9 +553,11 @@ def bench_jerk(args, torch, w):
     r0 = res[head]
     return {
         "value": pairs * args.steps / r0["wall"], "ms_per_step": r0["wall"] / args.steps * 1e3,
-        "config": {"workload": w.name, "n": n, "eps": eps, "seed": w.seed, "precision": head,
-                   "step": "one force+jerk+potential evaluation from FP64 positions and "
-                           "velocities (system centres, FP32 pair arithmetic)",
+        "config": {"workload": w.name, "n": n, "eps": eps, "seed": w.seed, "dt": dt,
+                   "precision": head,
+                   "step": "one graph-replayed fourth-order Hermite step: FP64 predictor, one "
+                           "N^2 force+jerk evaluation (FP32 pair arithmetic relative to the "
+                           "mean position and velocity), FP64 corrector",
                    "description": w.description},
         "roofline": roofline("jerk", pairs, r0["kernel_ms"],
                              "tile_kernel<GravityJerk> (+ jerk_finalize_kernel)"),

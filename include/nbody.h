@@ -55,7 +55,8 @@ typedef int32_t nbody_status;
 
 /* Accumulation of the pair terms of one i-particle (Sec. 2.2.2 and Sec. 3.4). */
 #define NBODY_PLAIN 0   /* one FP32 accumulator per j-segment; segments summed in FP32
-                           ("DIRECT style" when there is one segment)                  */
+                           (the paper's direct order with one segment, its FORCE-LOOP
+                           of eq. (2) with 512-j segments)                              */
 #define NBODY_FP64RED 1 /* FP32 partial over each block of j, added into FP64 registers
                            (the FORCE-LOOP of eq. (2) with an FP64 force memory)        */
 #define NBODY_COMP 2    /* FP32 partial over each block of j, added into an FP32
@@ -216,6 +217,33 @@ NBODY_API nbody_status nbody_graph_create_leapfrog(int64_t n, double *pos64, dou
                                                    nbody_graph **out);
 NBODY_API nbody_status nbody_graph_launch(nbody_graph *graph, void *stream);
 NBODY_API void nbody_graph_destroy(nbody_graph *graph);
+
+/* Fourth-order Hermite integration with a shared step (the integrator the force-jerk
+ * interaction serves, Sec. 5.1), in the predictor-evaluate-corrector form of Makino &
+ * Aarseth (1992), on FP64 state:
+ *   x_p = x + v dt + a dt^2/2 + j dt^3/6,  v_p = v + a dt + j dt^2/2,
+ *   (a1, j1) = force and jerk at (x_p, v_p)   (nbody_force_jerk_f64 arithmetic),
+ *   v' = v + (a + a1) dt/2 + (j - j1) dt^2/12,  x' = x + (v + v') dt/2 + (a - a1) dt^2/12,
+ *   (a, j) <- (a1, j1).
+ *   pos64, vel64  double [3][n], advanced nsteps steps in place
+ *   acc, jerk     double [3][n]: a and j at the entry state (or computed first when
+ *                 flags has NBODY_LF_INIT_ACC); on return those of the last evaluation,
+ *                 which the next call continues from
+ *   opts          precision, centre (NONE or SYSTEM; TILE gives NBODY_EUNSUPPORTED),
+ *                 ipl, jtile, nseg, workspace (nbody_workspace_size_hermite bytes)
+ * One force-jerk evaluation per step.  nbody_graph_create_hermite captures nsteps steps
+ * (without the initial evaluation) into a graph that owns its scratch; replay it with
+ * nbody_graph_launch and free it with nbody_graph_destroy. */
+NBODY_API nbody_status nbody_hermite(int64_t n, double *pos64, double *vel64, const float *mass,
+                                     float eps, double dt, int32_t nsteps, double *acc,
+                                     double *jerk, int32_t flags, const nbody_opts *opts,
+                                     void *stream);
+NBODY_API nbody_status nbody_graph_create_hermite(int64_t n, double *pos64, double *vel64,
+                                                  const float *mass, float eps, double dt,
+                                                  int32_t nsteps, double *acc, double *jerk,
+                                                  const nbody_opts *opts, void *stream,
+                                                  nbody_graph **out);
+NBODY_API size_t nbody_workspace_size_hermite(int64_t n, const nbody_opts *opts);
 
 /* ------------------------------------------------------------------------------
  * Adjoint (vector-Jacobian product) of one force evaluation.  Given cotangents

@@ -77,6 +77,10 @@ SIGNATURES = {
     "nbody_force_jerk": (_I32, [_I64, _P, _P, _P, _F, _P, _P, _P, _OPTS, _P]),
     "nbody_force_jerk_f64": (_I32, [_I64, _P, _P, _P, _F, _P, _P, _P, _OPTS, _P]),
     "nbody_workspace_size_jerk": (ctypes.c_size_t, [_I64, _OPTS]),
+    "nbody_hermite": (_I32, [_I64, _P, _P, _P, _F, _D, _I32, _P, _P, _I32, _OPTS, _P]),
+    "nbody_graph_create_hermite": (_I32, [_I64, _P, _P, _P, _F, _D, _I32, _P, _P, _OPTS, _P,
+                                          ctypes.POINTER(_P)]),
+    "nbody_workspace_size_hermite": (ctypes.c_size_t, [_I64, _OPTS]),
     "nbody_leapfrog": (_I32, [_I64, _P, _P, _P, _F, _D, _I32, _P, _P, _P, _I32, _OPTS, _P]),
     "nbody_graph_create_leapfrog": (_I32, [_I64, _P, _P, _P, _F, _D, _I32, _P, _P, _OPTS, _P,
                                            ctypes.POINTER(_P)]),
@@ -200,6 +204,26 @@ def nbody_force_jerk_f64(n, pos64, vel64, mass, eps, acc, jerk, pot, opts, strea
 
 def nbody_workspace_size_jerk(n: int, opts: nbody_opts | None) -> int:
     return int(load().nbody_workspace_size_jerk(n, _opt_ref(opts)))
+
+
+def nbody_hermite(n, pos64, vel64, mass, eps, dt, nsteps, acc, jerk, flags, opts, stream,
+                  check=True):
+    st = load().nbody_hermite(n, pos64, vel64, mass, eps, dt, nsteps, acc, jerk, flags,
+                              _opt_ref(opts), stream)
+    return _check(st, "nbody_hermite") if check else st
+
+
+def nbody_graph_create_hermite(n, pos64, vel64, mass, eps, dt, nsteps, acc, jerk, opts, stream):
+    """Returns the graph handle (an integer address)."""
+    h = ctypes.c_void_p()
+    st = load().nbody_graph_create_hermite(n, pos64, vel64, mass, eps, dt, nsteps, acc, jerk,
+                                           _opt_ref(opts), stream, ctypes.byref(h))
+    _check(st, "nbody_graph_create_hermite")
+    return h.value
+
+
+def nbody_workspace_size_hermite(n: int, opts: nbody_opts | None) -> int:
+    return int(load().nbody_workspace_size_hermite(n, _opt_ref(opts)))
 
 
 def _opt_ref(opts):

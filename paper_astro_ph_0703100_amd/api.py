@@ -201,6 +201,47 @@ class LeapfrogGraph:
             pass
 
 
+def hermite(pos64: torch.Tensor, vel64: torch.Tensor, mass: torch.Tensor, eps: float, dt: float,
+            nsteps: int, acc: torch.Tensor | None = None, jerk: torch.Tensor | None = None,
+            init: bool = True, precision: str = "comp", centre: str = "system", **kw):
+    """``nsteps`` fourth-order Hermite steps on ``pos64``/``vel64`` in place.
+
+    Returns ``(acc, jerk)`` of the last evaluation ``[3, n]``; with ``init=False`` they
+    must hold a and j at the entry state (as returned by a previous call).
+    """
+    n = _check_pos(pos64, torch.float64, "pos64")
+    _check_pos(vel64, torch.float64, "vel64")
+    _check_vec(mass, n, torch.float32, "mass")
+    dev = pos64.device
+    if acc is None:
+        acc = torch.empty((3, n), dtype=torch.float64, device=dev)
+    if jerk is None:
+        jerk = torch.empty((3, n), dtype=torch.float64, device=dev)
+    opts = make_opts(precision=precision, centre=centre, **kw)
+    _lib.nbody_hermite(n, pos64.data_ptr(), vel64.data_ptr(), mass.data_ptr(), float(eps),
+                       float(dt), int(nsteps), acc.data_ptr(), jerk.data_ptr(),
+                       _lib.NBODY_LF_INIT_ACC if init else 0, opts, stream_ptr())
+    return acc, jerk
+
+
+class HermiteGraph(LeapfrogGraph):
+    """A HIP graph of ``nsteps`` Hermite steps on fixed tensors (replayed by ``launch``);
+    ``acc`` and ``jerk`` must hold a and j at the state before the first launch."""
+
+    def __init__(self, pos64, vel64, mass, eps, dt, nsteps, acc, jerk, precision="comp",
+                 centre="system", **kw):
+        n = _check_pos(pos64, torch.float64, "pos64")
+        _check_pos(vel64, torch.float64, "vel64")
+        _check_pos(acc, torch.float64, "acc")
+        _check_pos(jerk, torch.float64, "jerk")
+        _check_vec(mass, n, torch.float32, "mass")
+        self._keep = (pos64, vel64, mass, acc, jerk)
+        opts = make_opts(precision=precision, centre=centre, **kw)
+        self.handle = _lib.nbody_graph_create_hermite(
+            n, pos64.data_ptr(), vel64.data_ptr(), mass.data_ptr(), float(eps), float(dt),
+            int(nsteps), acc.data_ptr(), jerk.data_ptr(), opts, stream_ptr())
+
+
 class BatchPlan:
     """Plan for a ragged batch of independent systems (see ``nbody_plan_create_batched``).
 

@@ -1,7 +1,9 @@
 // Host entry points of the force-jerk-potential path: argument checks, launch shape,
-// scratch, and (for FP64 state) the reference centres of positions and velocities.
+// scratch, and (for FP64 state) the reference centres of positions and velocities;
+// and the fourth-order Hermite integrator built on it (eager and captured in a graph).
 #include <cfloat>
 #include <cmath>
+#include <new>
 
 #include "nbody_internal.h"
 #include "tuning.h"
@@ -64,6 +66,80 @@ nbody_status jerk_core(int64_t n, const float *pos, const float *vel, const floa
     return launch_jerk_finalize(o.precision, fa, s);
 }
 
+// One evaluation from FP64 state: centres and FP32 conversion per opts.centre, then
+// the pair kernel and the FP64 finalize.
+nbody_status jerk_f64_core(int64_t n, const double *pos64, const double *vel64, const float *mass,
+                           float eps, double *acc, double *jerk, double *pot, const nbody_opts &o,
+                           const TileCfg &cfg, const JerkScratch &w, hipStream_t s) {
+    nbody_status st;
+    if (o.centre == NBODY_CENTRE_SYSTEM) {
+        // Positions relative to the FP64 mean position, velocities relative to the FP64
+        // mean velocity: differences of the shifted values are what the pairs need.
+        if ((st = launch_centre(n, pos64, w.cx, w.cscratch, s))) return st;
+        if ((st = launch_convert(n, pos64, w.cx, w.x32, s))) return st;
+        if ((st = launch_centre(n, vel64, w.cv, w.cscratch, s))) return st;
+        if ((st = launch_convert(n, vel64, w.cv, w.v32, s))) return st;
+    } else {
+        if ((st = launch_convert(n, pos64, nullptr, w.x32, s))) return st;
+        if ((st = launch_convert(n, vel64, nullptr, w.v32, s))) return st;
+    }
+    return jerk_core(n, w.x32, w.v32, mass, eps, acc, jerk, pot, o, cfg, w.part, s);
+}
+
+// Hermite scratch: the evaluation's scratch, then predicted state and new (a, j).
+struct HermiteScratch {
+    JerkScratch eval;
+    double *xp, *vp, *a1, *j1;
+};
+
+size_t hermite_bytes(int64_t n, const TileCfg &c, int precision) {
+    return jerk_f64_bytes(n, c, precision) + 4 * align_up(sizeof(double) * 3 * (size_t)n, 256);
+}
+
+HermiteScratch hermite_layout(void *ws, int64_t n, const TileCfg &c, int precision) {
+    HermiteScratch h;
+    h.eval = jerk_f64_layout(ws, n, c, precision);
+    char *b = static_cast<char *>(ws) + jerk_f64_bytes(n, c, precision);
+    const size_t vb = align_up(sizeof(double) * 3 * (size_t)n, 256);
+    h.xp = reinterpret_cast<double *>(b);
+    h.vp = reinterpret_cast<double *>(b + vb);
+    h.a1 = reinterpret_cast<double *>(b + 2 * vb);
+    h.j1 = reinterpret_cast<double *>(b + 3 * vb);
+    return h;
+}
+
+nbody_status check_hermite(int64_t n, const double *x, const double *v, const float *m, float eps,
+                           double dt, int32_t nsteps, const double *acc, const double *jerk,
+                           const nbody_opts &o) {
+    nbody_status st = check_jerk(n, x, v, m, eps, acc, jerk, o);
+    if (st) return st;
+    if (nsteps < 0) return set_error(NBODY_EINVAL, "nsteps must be >= 0");
+    if (!std::isfinite(dt)) return set_error(NBODY_EINVAL, "dt must be finite");
+    if (o.centre == NBODY_CENTRE_TILE)
+        return set_error(NBODY_EUNSUPPORTED, "the Hermite path supports NBODY_CENTRE_NONE and _SYSTEM");
+    if (misaligned(x) || misaligned(v) || misaligned(m) || misaligned(acc) || misaligned(jerk))
+        return set_error(NBODY_EINVAL, "misaligned array argument");
+    return NBODY_OK;
+}
+
+// Enqueues nsteps predictor-evaluate-corrector steps (after the initial evaluation if
+// `init`); (acc, jerk) must hold a and j at (x, v) when a step starts.
+nbody_status enqueue_hermite(int64_t n, double *x, double *v, const float *m, float eps, double dt,
+                             int32_t nsteps, double *acc, double *jerk, bool init,
+                             const nbody_opts &o, const TileCfg &cfg, const HermiteScratch &h,
+                             hipStream_t s) {
+    nbody_status st;
+    if (init && (st = jerk_f64_core(n, x, v, m, eps, acc, jerk, nullptr, o, cfg, h.eval, s)))
+        return st;
+    for (int32_t t = 0; t < nsteps; ++t) {
+        if ((st = launch_hermite_predict(n, x, v, acc, jerk, dt, h.xp, h.vp, s))) return st;
+        if ((st = jerk_f64_core(n, h.xp, h.vp, m, eps, h.a1, h.j1, nullptr, o, cfg, h.eval, s)))
+            return st;
+        if ((st = launch_hermite_correct(n, x, v, acc, jerk, h.a1, h.j1, dt, s))) return st;
+    }
+    return NBODY_OK;
+}
+
 }  // namespace
 }  // namespace nbody
 
@@ -116,19 +192,77 @@ nbody_status nbody_force_jerk_f64(int64_t n, const double *pos64, const double *
     if ((st = choose_cfg(KERNEL_JERK, n, o.precision, o, &cfg))) return st;
     void *ws = nullptr;
     if ((st = get_workspace(o, jerk_f64_bytes(n, cfg, o.precision), s, &ws))) return st;
-    const JerkScratch w = jerk_f64_layout(ws, n, cfg, o.precision);
-    if (o.centre == NBODY_CENTRE_SYSTEM) {
-        // Positions relative to the FP64 mean position, velocities relative to the FP64
-        // mean velocity: differences of the shifted values are what the pairs need.
-        if ((st = launch_centre(n, pos64, w.cx, w.cscratch, s))) return st;
-        if ((st = launch_convert(n, pos64, w.cx, w.x32, s))) return st;
-        if ((st = launch_centre(n, vel64, w.cv, w.cscratch, s))) return st;
-        if ((st = launch_convert(n, vel64, w.cv, w.v32, s))) return st;
-    } else {
-        if ((st = launch_convert(n, pos64, nullptr, w.x32, s))) return st;
-        if ((st = launch_convert(n, vel64, nullptr, w.v32, s))) return st;
+    return jerk_f64_core(n, pos64, vel64, mass, eps, acc, jerk, pot, o, cfg,
+                         jerk_f64_layout(ws, n, cfg, o.precision), s);
+}
+
+size_t nbody_workspace_size_hermite(int64_t n, const nbody_opts *opts) {
+    nbody_opts o = resolve_opts(opts);
+    if (n <= 0) return 0;
+    TileCfg c;
+    if (choose_cfg(KERNEL_JERK, n, o.precision, o, &c) != NBODY_OK) return 0;
+    return hermite_bytes(n, c, o.precision);
+}
+
+nbody_status nbody_hermite(int64_t n, double *pos64, double *vel64, const float *mass, float eps,
+                           double dt, int32_t nsteps, double *acc, double *jerk, int32_t flags,
+                           const nbody_opts *opts, void *stream) {
+    clear_error();
+    nbody_opts o = resolve_opts(opts);
+    nbody_status st = check_hermite(n, pos64, vel64, mass, eps, dt, nsteps, acc, jerk, o);
+    if (st) return st;
+    if (flags & ~NBODY_LF_INIT_ACC) return set_error(NBODY_EINVAL, "unknown flags");
+    if (n == 0) return NBODY_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    TileCfg cfg;
+    if ((st = choose_cfg(KERNEL_JERK, n, o.precision, o, &cfg))) return st;
+    void *ws = nullptr;
+    if ((st = get_workspace(o, hermite_bytes(n, cfg, o.precision), s, &ws))) return st;
+    return enqueue_hermite(n, pos64, vel64, mass, eps, dt, nsteps, acc, jerk,
+                           (flags & NBODY_LF_INIT_ACC) != 0, o, cfg,
+                           hermite_layout(ws, n, cfg, o.precision), s);
+}
+
+nbody_status nbody_graph_create_hermite(int64_t n, double *pos64, double *vel64, const float *mass,
+                                        float eps, double dt, int32_t nsteps, double *acc,
+                                        double *jerk, const nbody_opts *opts, void *stream,
+                                        nbody_graph **out) {
+    clear_error();
+    if (!out) return set_error(NBODY_EINVAL, "out must not be NULL");
+    *out = nullptr;
+    nbody_opts o = resolve_opts(opts);
+    nbody_status st = check_hermite(n, pos64, vel64, mass, eps, dt, nsteps, acc, jerk, o);
+    if (st) return st;
+    if (n == 0 || nsteps == 0) return set_error(NBODY_EINVAL, "graph needs n > 0 and nsteps > 0");
+    hipStream_t user = static_cast<hipStream_t>(stream);
+    if (stream_capturing(user)) return set_error(NBODY_ECAPTURE, "stream is already capturing");
+    TileCfg cfg;
+    if ((st = choose_cfg(KERNEL_JERK, n, o.precision, o, &cfg))) return st;
+    nbody_graph *g = new (std::nothrow) nbody_graph;
+    if (!g) return set_error(NBODY_ENOMEM, "out of host memory");
+    auto fail = [&](nbody_status code) {
+        if (g->exec) (void)hipGraphExecDestroy(g->exec);
+        if (g->graph) (void)hipGraphDestroy(g->graph);
+        if (g->workspace) (void)hipFree(g->workspace);
+        delete g;
+        return code;
+    };
+    hipError_t e = hipGetDevice(&g->device);
+    if (e != hipSuccess) return fail(hip_error(e, "hipGetDevice"));
+    // The graph owns its scratch: a shared cache could be reallocated under it.
+    const size_t need = hermite_bytes(n, cfg, o.precision);
+    if ((e = hipMalloc(&g->workspace, need)) != hipSuccess) {
+        g->workspace = nullptr;
+        return fail(hip_error(e, "hipMalloc(graph workspace)"));
     }
-    return jerk_core(n, w.x32, w.v32, mass, eps, acc, jerk, pot, o, cfg, w.part, s);
+    const HermiteScratch lay = hermite_layout(g->workspace, n, cfg, o.precision);
+    st = capture_graph(g, [&](hipStream_t cs) {
+        return enqueue_hermite(n, pos64, vel64, mass, eps, dt, nsteps, acc, jerk, false, o, cfg,
+                               lay, cs);
+    });
+    if (st) return fail(st);
+    *out = g;
+    return NBODY_OK;
 }
 
 }  // extern "C"

@@ -15,6 +15,7 @@ namespace {
 struct GravityJerk {
     static constexpr int kJWords = 8;
     static constexpr int kOut = 7;  // ax, ay, az, jx, jy, jz, phi
+    static constexpr int kBlockJ = 64;  // 14 two-sum operations per block of 64 pairs
     using Args = JerkArgs;
     struct IState {
         float x, y, z, vx, vy, vz;

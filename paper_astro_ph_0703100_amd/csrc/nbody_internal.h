@@ -25,7 +25,8 @@ namespace nbody {
 constexpr int kTPB = 256;
 // Largest number of j-segments a launch may split the j range into.
 constexpr int kMaxSeg = 1024;
-// j's summed in plain FP32 between two compensation / FP64 steps.
+// Default number of j's summed in plain FP32 between two compensation / FP64 steps; a
+// pipeline may set its own (Op::kBlockJ), and the engine caps it at the j-tile.
 constexpr int kBlockJ = 32;
 
 // Words (4-byte) of partial sums written per i-particle and j-segment.
@@ -278,6 +279,12 @@ nbody_status launch_batched_convert(int64_t total, const double *pos64, const in
 nbody_status launch_jerk(const TileCfg &cfg, int precision, bool with_pot, const JerkArgs &a,
                          hipStream_t s);
 nbody_status launch_jerk_finalize(int precision, const JerkFinalizeArgs &a, hipStream_t s);
+// Fourth-order Hermite predictor and corrector (hermite.hip).
+nbody_status launch_hermite_predict(int64_t n, const double *x, const double *v, const double *a,
+                                    const double *j, double dt, double *xp, double *vp,
+                                    hipStream_t s);
+nbody_status launch_hermite_correct(int64_t n, double *x, double *v, double *a, double *j,
+                                    const double *a1, const double *j1, double dt, hipStream_t s);
 // Adjoint pair kernel and its FP64 finalize (vjp.hip).
 nbody_status launch_vjp(const TileCfg &cfg, int precision, const VjpArgs &a, bool with_mass,
                         hipStream_t s);

@@ -1,7 +1,7 @@
 // Generic i-tile x j-tile pair engine for gfx950 (device code, header-only).
 //
-// The paper's library evaluates arbitrary pair interactions from a user "pipeline
-// description" that reads an i-record and a j-record and accumulates outputs
+// The paper's library evaluates arbitrary pair interactions from a user-written pipeline
+// description that reads an i-record and a j-record and accumulates outputs
 // (Sec. 4.5, Appendix A).  This engine is that idea on CDNA4: a pipeline type `Op`
 // supplies the records and the pair body; the engine supplies the blocking.
 //
@@ -17,7 +17,7 @@
 //     (potential-type) self term on its own so their finalize can remove it exactly;
 //   * accumulation (Sec. 2.2.2, eq. (2); Sec. 3.4):
 //       PLAIN   - one FP32 accumulator per output and (i, segment);
-//       FP64RED - FP32 partial over each block of kBlockJ j's, added into FP64;
+//       FP64RED - FP32 partial over each block of min(Op::kBlockJ, JT) j's, added into FP64;
 //       COMP    - FP32 partial over each block, added into an FP32 (hi, lo) pair by an
 //                 error-free two-sum;
 //   * partial sums go to scratch planes [segment][word][npad]; a finalize kernel adds
@@ -26,7 +26,8 @@
 //
 // An Op provides:
 //   static constexpr int kJWords;            // floats per j-record (multiple of 4)
-//   static constexpr int kOut;               // outputs per i (<= 4)
+//   static constexpr int kOut;               // outputs per i
+//   static constexpr int kBlockJ;            // j's per FP32 block before compensation
 //   struct Args;                             // kernel arguments (seg_len, eps2, part, npad, ...)
 //   static int n_i(const Args&), n_j(const Args&);  // i- and j-counts of a grid launch
 //   struct IState;                           // per-i registers
@@ -82,14 +83,18 @@ __device__ __forceinline__ void tile_pass(const float4 *tl, const typename Op::I
             for (int k = 0; k < IPL; ++k) Op::template pair<FULL>(jr, is[k], eps2, hs[k]);
         }
     } else {
-        for (int jb = 0; jb < JT; jb += kBlockJ) {
+        constexpr int BJ = JT < Op::kBlockJ ? JT : Op::kBlockJ;
+        static_assert(JT % BJ == 0, "blocks tile the j-tile");
+        for (int jb = 0; jb < JT; jb += BJ) {
             float bs[IPL][NO];
 #pragma unroll
             for (int k = 0; k < IPL; ++k)
 #pragma unroll
                 for (int c = 0; c < NO; ++c) bs[k][c] = -0.0f;
-#pragma unroll
-            for (int jj = 0; jj < kBlockJ; ++jj) {
+            // Unrolled 32 pairs deep: longer blocks loop over that body (a scalar
+            // branch per 32 pairs) instead of growing the code and the build time.
+#pragma unroll 32
+            for (int jj = 0; jj < BJ; ++jj) {
                 float jr[W];
                 read(jb + jj, jr);
 #pragma unroll

@@ -22,6 +22,7 @@ namespace {
 struct Adjoint {
     static constexpr int kJWords = 8;  // x, y, z, m, gx, gy, gz, p
     static constexpr int kOut = 4;     // dL/dx (3) and the positive sum of dL/dm
+    static constexpr int kBlockJ = nbody::kBlockJ;
     using Args = VjpArgs;
     struct IState {
         float x, y, z, m, gx, gy, gz, p;

@@ -249,9 +249,9 @@ WORKLOADS = {
                     "distribution-function velocities, eps=0.4/N^(1/3); force+potential and "
                     "KDK leapfrog steps dt=1/256"),
     "jerk_131072": Workload(
-        "jerk_131072", 131072, plummer_131072_eps(131072), 2,
-        description="N=131072 Plummer as plummer_131072 (same seed and eps); one "
-                    "force+jerk+potential evaluation from FP64 positions and velocities"),
+        "jerk_131072", 131072, plummer_131072_eps(131072), 2, dt=1.0 / 256.0, steps=8,
+        description="N=131072 Plummer as plummer_131072 (same seed and eps); fourth-order "
+                    "Hermite steps dt=1/256, one force+jerk evaluation each"),
     "stress_1m": Workload(
         "stress_1m", 1 << 20, 1e-4, 3,
         description="N=2^20 halo + 10%-mass core of scale 1e-3 at (1000,0,0), log-uniform "

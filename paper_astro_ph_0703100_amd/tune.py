@@ -1,7 +1,8 @@
 """Autotuner: measure launch shapes on the GPU and write the library's tuning table.
 
 For each workload it sweeps i-particles per lane (1, 2, 4, 8), j-tile (64 .. 512)
-and, for the single-system kernels, the number of j-segments; times every shape with
+and, for the single-system kernels (force, force-jerk, adjoint), the number of
+j-segments; times every shape with
 HIP events on the launch stream (median of ``reps`` after a warm-up call); and admits
 a shape only if its result matches a reference computed on the same GPU with FP64
 reduction at the built-in shape (relative RMS <= 1e-6, plain FP32 <= 2e-5).  The
@@ -25,7 +26,7 @@ from .metrics import rel_errors
 
 IPLS = (1, 2, 4, 8)
 JTILES = (64, 128, 256, 512)
-SEGS = (0, 4, 8, 10, 12, 16, 20, 24, 32, 40, 48, 64)
+SEGS = (0, 4, 8, 10, 12, 16, 20, 24, 32, 40, 48, 64, 96, 128)
 GATE = {"comp": 1e-6, "fp64red": 1e-6, "plain": 2e-5}
 
 
@@ -77,6 +78,44 @@ def tune_force(n: int, seed: int, eps: float, precision: str, reps: int = 3, log
                 ok = ea <= GATE[precision] and ep <= GATE[precision]
                 row = {"kernel": "force", "precision": precision, "n": n, "ipl": ipl,
                        "jtile": jt, "nseg": nseg, "ms": ms, "acc_rel_rms": ea, "ok": ok,
+                       "pairs_per_s": n * n / (ms * 1e-3)}
+                rows.append(row)
+                if log:
+                    log(row)
+                if ok and (best is None or ms < best["ms"]):
+                    best = row
+    return best, rows
+
+
+def tune_jerk(n: int, seed: int, eps: float, precision: str, reps: int = 3, log=None):
+    """Sweep the force-jerk-potential kernel for ``n`` particles (with velocities)."""
+    pos, vel, mass = ics.plummer(n, seed=seed)
+    dev = "cuda:0"
+    p = torch.from_numpy(np.ascontiguousarray(pos.T.astype(np.float32))).to(dev)
+    v = torch.from_numpy(np.ascontiguousarray(vel.T.astype(np.float32))).to(dev)
+    m = torch.from_numpy(mass.astype(np.float32)).to(dev)
+    ref_a, ref_j, _ = api.force_jerk(p, v, m, eps, precision="fp64red", ipl=1, jtile=64, nseg=1)
+    ref_a, ref_j = _host(ref_a).T.copy(), _host(ref_j).T.copy()
+    acc = torch.empty((3, n), dtype=torch.float64, device=dev)
+    jerk = torch.empty((3, n), dtype=torch.float64, device=dev)
+    pot = torch.empty(n, dtype=torch.float64, device=dev)
+    best, rows = None, []
+    for ipl in IPLS:
+        for jt in JTILES:
+            jtiles = (n + jt - 1) // jt
+            for nseg in SEGS:
+                if nseg > jtiles:
+                    continue
+                opts = api.make_opts(precision=precision, ipl=ipl, jtile=jt, nseg=nseg)
+                call = lambda: _lib.nbody_force_jerk(n, p.data_ptr(), v.data_ptr(), m.data_ptr(),
+                                                     eps, acc.data_ptr(), jerk.data_ptr(),
+                                                     pot.data_ptr(), opts, api.stream_ptr())
+                ms = _time(call, reps)
+                ea = rel_errors(_host(acc).T, ref_a)["rel_rms"]
+                ej = rel_errors(_host(jerk).T, ref_j)["normwise"]
+                ok = ea <= GATE[precision] and ej <= 10 * GATE[precision]
+                row = {"kernel": "jerk", "precision": precision, "n": n, "ipl": ipl, "jtile": jt,
+                       "nseg": nseg, "ms": ms, "acc_rel_rms": ea, "jerk_normwise": ej, "ok": ok,
                        "pairs_per_s": n * n / (ms * 1e-3)}
                 rows.append(row)
                 if log:
@@ -165,10 +204,18 @@ def main(argv=None):
     ap.add_argument("--report", default="", help="write every measured shape here (JSON lines)")
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--quick", action="store_true", help="force kernel at N=131072 only")
+    ap.add_argument("--only", default="",
+                    help="comma-separated kernels to tune (force, jerk, vjp, batched); the other "
+                         "entries of the table at --out are kept")
     args = ap.parse_args(argv)
 
     _lib.load()
-    _lib.nbody_tune_reset()  # measure against the built-in shapes, not an old table
+    only = [k for k in args.only.split(",") if k]
+    if only and os.path.exists(args.out):
+        _lib.nbody_tune_reset()
+        _lib.nbody_tune_load(args.out)  # keep the entries that are not re-tuned
+    else:
+        _lib.nbody_tune_reset()  # measure against the built-in shapes, not an old table
     rep = open(args.report, "w") if args.report else None
 
     def log(row):
@@ -184,12 +231,15 @@ def main(argv=None):
     if not args.quick:
         for n in (2048, 16384, 32768):
             jobs.append(("force", "comp", lambda n=n: tune_force(n, 10 + n, 0.01, "comp", args.reps, log)))
+        jobs.append(("jerk", "comp", lambda: tune_jerk(w.n, w.seed, eps, "comp", args.reps, log)))
         wa = ics.WORKLOADS["adjoint_16384"]
         jobs.append(("vjp", "comp", lambda: tune_vjp(wa.n, wa.seed, float(np.float32(wa.eps)), "comp",
                                                      args.reps, log)))
         wb = ics.WORKLOADS["clusters_2048"]
         jobs.append(("batched", "comp", lambda: tune_batched(wb.n, wb.seed, wb.eps, "comp",
                                                              args.reps, log)))
+    if only:
+        jobs = [j for j in jobs if j[0] in only]
     summary = []
     for kernel, prec, job in jobs:
         best, rows = job()

@@ -1,0 +1,43 @@
+"""Host-side checks of the benchmark script's contract (no GPU needed)."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "4"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+def test_roofline_fields():
+    pairs = 131072.0 ** 2
+    r = bench.roofline("gravity", pairs, 5.0, "k", traffic=123)
+    assert r["bound"] == "alu" and r["unit"] == "TFLOP/s" and r["traffic"] == 123
+    # 17 issue slots per pair at 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz, 20 flop per pair.
+    assert r["peak"] == pytest.approx(256 * 4 * 32 * 2.4e9 / 17 * 20 / 1e12)
+    assert r["achieved"] == pytest.approx(pairs * 20 / 5e-3 / 1e12)
+    assert r["frac"] == pytest.approx(r["achieved"] / r["peak"])
+    for kind, slots in (("jerk", 31), ("adjoint", 42)):
+        assert bench.peak_pairs(kind) == pytest.approx(256 * 4 * 32 * 2.4e9 / slots)
+
+
+def test_committed_traffic_matches_the_current_sources():
+    # The counter summary of the pair kernel carries the hash of the kernel sources and
+    # launch shape it was measured with; the bench reports its traffic only while they match.
+    text = open(bench.TRAFFIC_SUMMARY).read()
+    rec = json.loads(text.split("<!-- traffic: ")[1].split(" -->")[0])
+    assert rec["bytes_per_launch"] > 0
+    if rec["sources_hash"] == bench.sources_hash():
+        assert bench.committed_traffic() == rec["bytes_per_launch"]
+    else:
+        assert bench.committed_traffic() is None
