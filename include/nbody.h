@@ -150,7 +150,7 @@ NBODY_API size_t nbody_workspace_size_ij(int64_t ni, int64_t nj, const nbody_opt
 /* ------------------------------------------------------------------------------
  * Force, jerk and potential in one pass: the force-jerk-potential pipeline of the
  * paper's Appendix A, the interaction a fourth-order Hermite integrator needs
- * (Sec. 5.1).  With d = x_j - x_i, w = v_j - v_i, s^2 = |d|^2 + eps^2:
+ * (Sec. 4.1).  With d = x_j - x_i, w = v_j - v_i, s^2 = |d|^2 + eps^2:
  *   a_i = sum m_j d / s^3,  jerk_i = sum m_j (w / s^3 - 3 (d.w) d / s^5),
  *   phi_i = -sum m_j / s,
  * all i against all j of one system, j == i excluded as in nbody_force (self_pot = 1
@@ -219,7 +219,7 @@ NBODY_API nbody_status nbody_graph_launch(nbody_graph *graph, void *stream);
 NBODY_API void nbody_graph_destroy(nbody_graph *graph);
 
 /* Fourth-order Hermite integration with a shared step (the integrator the force-jerk
- * interaction serves, Sec. 5.1), in the predictor-evaluate-corrector form of Makino &
+ * interaction serves, Sec. 4.1), in the predictor-evaluate-corrector form of Makino &
  * Aarseth (1992), on FP64 state:
  *   x_p = x + v dt + a dt^2/2 + j dt^3/6,  v_p = v + a dt + j dt^2/2,
  *   (a1, j1) = force and jerk at (x_p, v_p)   (nbody_force_jerk_f64 arithmetic),

@@ -121,7 +121,7 @@ OR_EXPORT void oracle_force_sampled(int64_t n, const double *x, const double *m,
 
 /* ------------------------------------------------------------------------- */
 /* Force, jerk and potential (the force-jerk-potential pipeline of Appendix A, */
-/* the interaction a fourth-order Hermite integrator needs, Sec. 5.1).  With   */
+/* the interaction a fourth-order Hermite integrator needs, Sec. 4.1).  With   */
 /* d = x_j - x_i, w = v_j - v_i and s^2 = |d|^2 + eps^2, the time derivative   */
 /* of the pair acceleration m_j d / s^3 along the motion is                     */
 /*   jerk_ij = m_j ( w / s^3 - 3 (d . w) d / s^5 ).                              */
@@ -373,7 +373,7 @@ OR_EXPORT void oracle_fp32_replay(int64_t n, const float *x, const float *m, flo
 
 /* ------------------------------------------------------------------------- */
 /* Fourth-order Hermite integration with a shared step (the integrator the     */
-/* paper's force-jerk interaction serves, Sec. 5.1), in the predictor-         */
+/* paper's force-jerk interaction serves, Sec. 4.1), in the predictor-         */
 /* evaluate-corrector form of Makino & Aarseth (1992):                          */
 /*   x_p = x + v dt + a dt^2/2 + j dt^3/6,   v_p = v + a dt + j dt^2/2          */
 /*   (a1, j1) = F(x_p, v_p)                                                     */

@@ -1,5 +1,5 @@
 // Force, jerk and potential in one pass: the force-jerk-potential pipeline of the
-// paper's Appendix A (the interaction of a fourth-order Hermite integrator, Sec. 5.1)
+// paper's Appendix A (the interaction of a fourth-order Hermite integrator, Sec. 4.1)
 // on the tile engine.  With d = x_j - x_i, w = v_j - v_i and s^2 = |d|^2 + eps^2:
 //   a_i    +=  m_j d / s^3
 //   jerk_i +=  m_j (w - 3 (d.w / s^2) d) / s^3
