@@ -19,6 +19,9 @@ step evaluates):
                  step (persistent work-queue kernel); pairs = sum N_k^2.
   adjoint_16384  N = 16384, 32 KDK steps dt = 1/256 and the reverse pass; step = one
                  loss + gradient (33 force and 33 adjoint evaluations of N^2 pairs).
+  shard8_131072  one GPU's share of an 8-way i-split of the N = 131072 sphere: force and
+                 potential on 16384 i-particles from all 131072 (separate i- and j-sets);
+                 step = one evaluation.
   jerk_131072    the N = 131072 sphere; step = one graph-replayed fourth-order Hermite
                  step (dt = 1/256): FP64 predictor, one N^2 force+jerk evaluation from
                  the predicted state, FP64 corrector.
@@ -113,7 +116,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="plummer_131072",
                     choices=["plummer_131072", "plummer_2048", "stress_1m", "clusters_2048",
-                             "adjoint_16384", "jerk_131072"])
+                             "adjoint_16384", "jerk_131072", "shard8_131072"])
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the FP64 oracle leg (no errors, no CPU rate)")
     ap.add_argument("--cpu-sample", type=int, default=0,
@@ -483,6 +486,72 @@ def bench_adjoint(args, torch, w):
     }
 
 
+def bench_shard(args, torch, w):
+    from paper_astro_ph_0703100_amd import _lib, api, ics, metrics
+    n, ni = w.n, w.n // 8
+    pos, _, mass = ics.plummer(n, seed=w.seed, velocities=False)
+    m32 = mass.astype(np.float32)
+    eps = float(np.float32(w.eps))
+    dev = torch.device("cuda:0")
+    p32 = np.ascontiguousarray(pos.T.astype(np.float32))
+    pj = torch.from_numpy(p32).to(dev)
+    pi = pj[:, :ni].contiguous()
+    m = torch.from_numpy(m32).to(dev)
+    acc = torch.empty((3, ni), dtype=torch.float64, device=dev)
+    pot = torch.empty(ni, dtype=torch.float64, device=dev)
+    sp = torch.cuda.current_stream().cuda_stream
+    timer = Timer(torch)
+    pairs = float(ni) * float(n)
+    res = {}
+    for precision in [s for s in args.modes.split(",") if s]:
+        opts = api.make_opts(precision=precision)
+        call = lambda: _lib.nbody_force_ij(ni, pi.data_ptr(), None, n, pj.data_ptr(), m.data_ptr(),
+                                           eps, acc.data_ptr(), pot.data_ptr(), opts, sp)
+        wall, kms = timer.run(call, args.steps, warmup=args.warmup)
+        res[precision] = {"wall": wall, "kernel_ms": float(np.mean(kms)),
+                          "acc": acc.cpu().numpy().T.copy(), "pot": pot.cpu().numpy().copy()}
+        print("bench: %-8s %d evaluations  %.3f ms each (wall)  %.3f ms (events)"
+              % (precision, args.steps, wall / args.steps * 1e3, np.mean(kms)),
+              file=sys.stderr, flush=True)
+    cpu, errors = None, {}
+    if not args.no_cpu_baseline:
+        import oracle
+        k = 2048 if args.cpu_sample <= 0 else min(ni, args.cpu_sample)
+        idx = ics.sample_indices(ni, k, seed=w.seed + 1000)
+        x64 = p32.T.astype(np.float64)
+        t0 = time.perf_counter()
+        ra, rp = oracle.force_ij(x64, m32.astype(np.float64), x64[idx], eps)
+        ct = time.perf_counter() - t0
+        cpu = {"value": k * float(n) / ct, "unit": "pair-interactions/s",
+               "cores": oracle.threads(), "kind": "oracle",
+               "sample": "force+potential of %d sampled i-particles of the shard from all %d, "
+                         "FP64 (%.1f s)" % (k, n, ct)}
+        i1 = idx[::8]
+        one_thread(cpu, lambda: oracle.force_ij(x64, m32.astype(np.float64), x64[i1], eps),
+                   float(i1.size) * n, "%d of those i-particles" % i1.size)
+        for p, r in res.items():
+            errors[p] = errors_of(metrics, r["acc"][idx], r["pot"][idx], ra, rp)
+    head = next(iter(res))
+    r0 = res[head]
+    return {
+        "value": pairs * args.steps / r0["wall"], "ms_per_step": r0["wall"] / args.steps * 1e3,
+        "config": {"workload": w.name, "n": n, "n_i": ni, "eps": eps, "seed": w.seed,
+                   "precision": head,
+                   "step": "one force+potential evaluation of the first 16384 particles from all "
+                           "131072 (nbody_force_ij, FP32 inputs); the self pair counts in the "
+                           "potential as for any separate i-set",
+                   "description": w.description},
+        "roofline": roofline("gravity", pairs, r0["kernel_ms"],
+                             "tile_kernel<GravityIJ> (+ finalize_kernel)"),
+        "cpu_baseline": cpu,
+        "modes": {p: {"value": pairs * args.steps / r["wall"],
+                      "ms_per_step": r["wall"] / args.steps * 1e3,
+                      "kernel_ms": r["kernel_ms"],
+                      "roofline_frac": pairs / (r["kernel_ms"] * 1e-3) / peak_pairs("gravity"),
+                      "errors": errors.get(p)} for p, r in res.items()},
+    }
+
+
 def bench_jerk(args, torch, w):
     from paper_astro_ph_0703100_amd import _lib, api, ics, metrics
     n = w.n
@@ -596,7 +665,8 @@ def main():
     w = ics.WORKLOADS[args.workload]
     fn = {"plummer_131072": bench_plummer, "plummer_2048": bench_plummer,
           "stress_1m": bench_stress, "clusters_2048": bench_clusters,
-          "adjoint_16384": bench_adjoint, "jerk_131072": bench_jerk}[w.name]
+          "adjoint_16384": bench_adjoint, "jerk_131072": bench_jerk,
+          "shard8_131072": bench_shard}[w.name]
     body = fn(args, torch, w)
     line = {
         "metric": METRIC if w.name == "plummer_131072" else "pair interactions/s, " + w.name,

@@ -1,5 +1,6 @@
 // Host side of the C ABI: argument validation, launch-shape choice, scratch memory
 // and dispatch to the kernels.  Nothing here touches particle data on the host.
+#include <algorithm>
 #include <cfloat>
 #include <cmath>
 #include <cstring>
@@ -129,11 +130,15 @@ nbody_status choose_cfg_ij(int kernel, int64_t ni, int64_t nj, int precision, co
     c.npad = (int)(c.itiles * itile);
     const int64_t jtiles = (nj + c.jt - 1) / c.jt;
     int64_t nseg = o.nseg ? o.nseg : (ni == nj ? t.nseg : 0);
-    if (nseg <= 0) {
-        // About 48 blocks per compute unit: enough to keep 8 waves per SIMD busy and to
-        // make the last round of blocks short (measured best at 40-64 per CU).
-        const int64_t target = (int64_t)device_info().cus * 48;
-        nseg = c.itiles > 0 ? (target + c.itiles - 1) / c.itiles : 1;
+    if (nseg <= 0 && c.itiles > 0) {
+        // Between 16 and 48 blocks per compute unit (8 resident per CU, so 2 to 6
+        // rounds: the last round stays short), and within that range segments of at
+        // least 8 j-tiles, so per-block start-up and the partial sums stay small when
+        // there are few i-tiles (an i-range of one system against all of it).
+        const int64_t cus = device_info().cus;
+        const int64_t hi = (cus * 48 + c.itiles - 1) / c.itiles;
+        const int64_t lo = (cus * 16 + c.itiles - 1) / c.itiles;
+        nseg = std::min(hi, std::max(lo, jtiles / 8));
     }
     if (nseg > jtiles) nseg = jtiles;
     if (nseg > kMaxSeg) nseg = kMaxSeg;

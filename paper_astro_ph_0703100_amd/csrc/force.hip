@@ -6,31 +6,31 @@ namespace nbody {
 namespace {
 
 // Fixed-order sum of the segment partials (PLAIN in FP32, the other modes in FP64),
-// then removal of the j == i potential term fl(m_i * rsq(eps^2)), recomputed with the
-// FP32 operations the pair body used for it (exact removal; the rounding that term
-// caused while it was in the sums is at most about u * m_i / eps).  With kick_v set,
-// the velocity kick of a leapfrog step follows in FP64.
+// one thread per (particle, output) so that few particles with many segments still
+// fill the chip; then removal of the j == i potential term fl(m_i * rsq(eps^2)),
+// recomputed with the FP32 operations the pair body used for it (exact removal; the
+// rounding that term caused while it was in the sums is at most about u * m_i / eps).
+// With kick_v set, the velocity kick of a leapfrog step follows in FP64.
+// Grid: (ceil(n / 256), 4 outputs, or 3 without potentials).
 template <int MODE>
 __global__ __launch_bounds__(256) void finalize_kernel(FinalizeArgs a) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
     if (i >= a.n) return;
-    double r[4];
-    engine::sum_partials<4, MODE>(a.part, a.nseg, (size_t)a.npad, i, r);
-    if (a.exclude_self) {
-        const float self = a.m[i] * __builtin_amdgcn_rsqf(a.eps2);
-        if constexpr (MODE == NBODY_PLAIN)
-            r[3] = (double)((float)r[3] + self);
-        else
-            r[3] += (double)self;
+    double r = engine::sum_partial_output<4, MODE>(a.part, a.nseg, (size_t)a.npad, i, c);
+    if (c == 3) {
+        if (a.exclude_self) {
+            const float self = a.m[i] * __builtin_amdgcn_rsqf(a.eps2);
+            if constexpr (MODE == NBODY_PLAIN)
+                r = (double)((float)r + self);
+            else
+                r += (double)self;
+        }
+        a.pot[i] = r;
+        return;
     }
-    a.acc[i] = r[0];
-    a.acc[(size_t)a.n + i] = r[1];
-    a.acc[2 * (size_t)a.n + i] = r[2];
-    if (a.pot) a.pot[i] = r[3];
-    if (a.kick_v) {  // second kick of a leapfrog step, fused: v += h a
-#pragma unroll
-        for (int c = 0; c < 3; ++c) a.kick_v[c * (size_t)a.n + i] += a.kick_h * r[c];
-    }
+    a.acc[c * (size_t)a.n + i] = r;
+    if (a.kick_v) a.kick_v[c * (size_t)a.n + i] += a.kick_h * r;  // second kick, fused: v += h a
 }
 
 // Two-stage fixed-order FP64 mean of the positions [3][n]: kCentreBlocks partial
@@ -136,7 +136,7 @@ nbody_status launch_pair(const TileCfg &cfg, int precision, bool with_pot, const
 
 nbody_status launch_finalize(int precision, const FinalizeArgs &a, hipStream_t s) {
     if (a.n <= 0) return NBODY_OK;
-    const dim3 grid((a.n + 255) / 256);
+    const dim3 grid((a.n + 255) / 256, a.pot ? 4 : 3);
     switch (precision) {
         case NBODY_PLAIN: hipLaunchKernelGGL(finalize_kernel<NBODY_PLAIN>, grid, dim3(256), 0, s, a); break;
         case NBODY_FP64RED: hipLaunchKernelGGL(finalize_kernel<NBODY_FP64RED>, grid, dim3(256), 0, s, a); break;

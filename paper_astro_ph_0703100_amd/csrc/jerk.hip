@@ -77,26 +77,30 @@ struct GravityJerk {
     }
 };
 
+// One thread per (particle, output): fixed-order sums as in the force finalize, the
+// j == i potential term removed exactly.  Grid: (ceil(n / 256), 7 outputs, or 6
+// without potentials).
 template <int MODE>
 __global__ __launch_bounds__(256) void jerk_finalize_kernel(JerkFinalizeArgs a) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
     if (i >= a.n) return;
-    double r[7];
-    engine::sum_partials<7, MODE>(a.part, a.nseg, (size_t)a.npad, i, r);
-    if (a.exclude_self) {
-        const float self = a.m[i] * __builtin_amdgcn_rsqf(a.eps2);
-        if constexpr (MODE == NBODY_PLAIN)
-            r[6] = (double)((float)r[6] + self);
-        else
-            r[6] += (double)self;
-    }
+    double r = engine::sum_partial_output<7, MODE>(a.part, a.nseg, (size_t)a.npad, i, c);
     const size_t n = (size_t)a.n;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        a.acc[c * n + i] = r[c];
-        a.jerk[c * n + i] = r[3 + c];
+    if (c == 6) {
+        if (a.exclude_self) {
+            const float self = a.m[i] * __builtin_amdgcn_rsqf(a.eps2);
+            if constexpr (MODE == NBODY_PLAIN)
+                r = (double)((float)r + self);
+            else
+                r += (double)self;
+        }
+        a.pot[i] = r;
+    } else if (c < 3) {
+        a.acc[c * n + i] = r;
+    } else {
+        a.jerk[(c - 3) * n + i] = r;
     }
-    if (a.pot) a.pot[i] = r[6];
 }
 
 }  // namespace
@@ -113,7 +117,7 @@ nbody_status launch_jerk(const TileCfg &cfg, int precision, bool with_pot, const
 
 nbody_status launch_jerk_finalize(int precision, const JerkFinalizeArgs &a, hipStream_t s) {
     if (a.n <= 0) return NBODY_OK;
-    const dim3 grid((a.n + 255) / 256);
+    const dim3 grid((a.n + 255) / 256, a.pot ? 7 : 6);
     switch (precision) {
         case NBODY_PLAIN: hipLaunchKernelGGL(jerk_finalize_kernel<NBODY_PLAIN>, grid, dim3(256), 0, s, a); break;
         case NBODY_FP64RED: hipLaunchKernelGGL(jerk_finalize_kernel<NBODY_FP64RED>, grid, dim3(256), 0, s, a); break;

@@ -289,6 +289,32 @@ __device__ __forceinline__ void sum_partials(const void *part, int nseg, size_t 
     }
 }
 
+// The same fixed-order sum for one output c of particle i (identical rounding to the
+// corresponding element of sum_partials), so a finalize can spread outputs over threads.
+template <int NO, int MODE>
+__device__ __forceinline__ double sum_partial_output(const void *part, int nseg, size_t plane,
+                                                     int i, int c) {
+    if constexpr (MODE == NBODY_PLAIN) {
+        float f = 0.0f;
+        const float *p = static_cast<const float *>(part) + i;
+        for (int s = 0; s < nseg; ++s) f = f + p[((size_t)s * NO + c) * plane];
+        return (double)f;
+    } else if constexpr (MODE == NBODY_COMP) {
+        const float *p = static_cast<const float *>(part) + i;
+        double r = 0.0;
+        for (int s = 0; s < nseg; ++s) {
+            r += (double)p[((size_t)s * 2 * NO + c) * plane];
+            r += (double)p[((size_t)s * 2 * NO + NO + c) * plane];
+        }
+        return r;
+    } else {
+        const double *p = static_cast<const double *>(part) + i;
+        double r = 0.0;
+        for (int s = 0; s < nseg; ++s) r += p[((size_t)s * NO + c) * plane];
+        return r;
+    }
+}
+
 // Launch-shape dispatch over the template parameters.
 template <class Op>
 using TileFn = void (*)(typename Op::Args);

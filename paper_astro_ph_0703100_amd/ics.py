@@ -248,6 +248,10 @@ WORKLOADS = {
         description="N=131072 Plummer (a=1, M=1, equal masses, truncated at 20) with "
                     "distribution-function velocities, eps=0.4/N^(1/3); force+potential and "
                     "KDK leapfrog steps dt=1/256"),
+    "shard8_131072": Workload(
+        "shard8_131072", 131072, plummer_131072_eps(131072), 2,
+        description="one GPU's share of an 8-way i-split of the N=131072 sphere (same seed "
+                    "and eps): 16384 i-particles against all 131072"),
     "jerk_131072": Workload(
         "jerk_131072", 131072, plummer_131072_eps(131072), 2, dt=1.0 / 256.0, steps=8,
         description="N=131072 Plummer as plummer_131072 (same seed and eps); fourth-order "
