@@ -63,6 +63,7 @@ METRIC = "pair interactions/s at N=131072, compensated vs plain FP32, error vs F
 # transcendental (v_rsq_f32) issues at a quarter of that rate, so it takes 4 slots.
 CUS, SIMDS, LANES, CLOCK_HZ = 256, 4, 32, 2.4e9
 LANE_ISSUE = CUS * SIMDS * LANES * CLOCK_HZ
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # the published FP32 vector figure (FMA = 2 flops)
 RSQ_SLOTS = 4
 SLOTS = {"gravity": 13 + RSQ_SLOTS, "jerk": 27 + RSQ_SLOTS, "adjoint": 38 + RSQ_SLOTS}
 # Flops per pair: the paper's count for gravity (Sec. 1.1); 60 for force, jerk and
@@ -182,6 +183,7 @@ def roofline(kind, pairs_per_launch, kernel_ms, kernel_name, traffic=None):
     peak = peak_pairs(kind) * FLOPS[kind] / 1e12
     return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
             "frac": achieved / peak, "traffic": traffic, "kernel": kernel_name,
+            "fp32_vector_peak_frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
             "kernel_ms": kernel_ms, "flops_per_pair": FLOPS[kind],
             "issue_slots_per_pair": SLOTS[kind], "peak_pairs_per_s": peak_pairs(kind)}
 
