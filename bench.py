@@ -97,8 +97,9 @@ def sources_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def committed_traffic():
-    """HBM bytes per launch of the pair kernel from the committed counter summary, or None."""
+def committed_record():
+    """The counter record of the pair kernel in the committed summary (HBM bytes per launch,
+    sustained clock), or None when the kernel sources or shape changed since."""
     try:
         text = open(TRAFFIC_SUMMARY).read()
     except OSError:
@@ -107,7 +108,13 @@ def committed_traffic():
     if not m:
         return None
     rec = json.loads(m.group(1))
-    return rec["bytes_per_launch"] if rec.get("sources_hash") == sources_hash() else None
+    return rec if rec.get("sources_hash") == sources_hash() else None
+
+
+def committed_traffic():
+    """HBM bytes per launch of the pair kernel from the committed counter summary, or None."""
+    rec = committed_record()
+    return rec["bytes_per_launch"] if rec else None
 
 
 def parse():
@@ -250,7 +257,13 @@ def bench_plummer(args, torch, w):
             errors[p] = errors_of(metrics, r["acc"][idx], r["pot"][idx], ra, rp)
     head = next(iter(res))
     r0 = res[head]
-    traffic = committed_traffic() if w.name == "plummer_131072" else None
+    rec = committed_record() if w.name == "plummer_131072" else None
+    roof = roofline("gravity", pairs, r0["kernel_ms"], "tile_kernel<Gravity> (+ finalize_kernel)",
+                    rec["bytes_per_launch"] if rec else None)
+    if rec and rec.get("sustained_clock_ghz"):
+        # The same roofline at the engine clock the counters measured under this load.
+        roof["sustained_clock_ghz"] = rec["sustained_clock_ghz"]
+        roof["frac_at_sustained_clock"] = roof["frac"] * CLOCK_HZ / (rec["sustained_clock_ghz"] * 1e9)
     return {
         "value": pairs * args.steps / r0["wall"], "ms_per_step": r0["wall"] / args.steps * 1e3,
         "config": {"workload": w.name, "n": n, "eps": eps, "seed": w.seed, "dt": dt,
@@ -258,8 +271,7 @@ def bench_plummer(args, torch, w):
                    "step": "one graph-replayed KDK leapfrog step: FP64 state, FP32 pair "
                            "arithmetic relative to the system centre, one N^2 force+potential "
                            "evaluation", "description": w.description},
-        "roofline": roofline("gravity", pairs, r0["kernel_ms"],
-                             "tile_kernel<Gravity> (+ finalize_kernel)", traffic),
+        "roofline": roof,
         "cpu_baseline": cpu,
         "modes": {p: {"value": pairs * args.steps / r["wall"],
                       "ms_per_step": r["wall"] / args.steps * 1e3,
