@@ -462,9 +462,22 @@ def bench_adjoint(args, torch, w):
     _, kms = timer.run(lambda: _lib.nbody_force_vjp(n, p32.data_ptr(), m32.data_ptr(), eps,
                                                     g.data_ptr(), None, gx.data_ptr(),
                                                     gm.data_ptr(), opts, sp), 8)
+    # The same kernel on the N = 131072 sphere, where the grid holds many rounds of blocks.
+    nb = 131072
+    xb, _, mb = ics.plummer(nb, seed=2, velocities=False)
+    pb = torch.from_numpy(np.ascontiguousarray(xb.T.astype(np.float32))).to(dev)
+    mbt = torch.from_numpy(mb.astype(np.float32)).to(dev)
+    gb = torch.from_numpy(np.random.default_rng(2).standard_normal((3, nb))).to(dev)
+    gxb = torch.empty((3, nb), dtype=torch.float64, device=dev)
+    gmb = torch.empty(nb, dtype=torch.float64, device=dev)
+    eb = float(np.float32(ics.plummer_131072_eps(nb)))
+    _, kmb = timer.run(lambda: _lib.nbody_force_vjp(nb, pb.data_ptr(), mbt.data_ptr(), eb,
+                                                    gb.data_ptr(), None, gxb.data_ptr(),
+                                                    gmb.data_ptr(), opts, sp), 3)
+    big = roofline("adjoint", float(nb) * nb, float(np.mean(kmb)), "tile_kernel<Adjoint>")
     pairs_step = float(n) * n * 2 * (w.steps + 1)
-    print("bench: rollout+gradient %.3f ms/step, adjoint kernel %.3f ms" %
-          (wall / args.steps * 1e3, np.mean(kms)), file=sys.stderr, flush=True)
+    print("bench: rollout+gradient %.3f ms/step, adjoint kernel %.3f ms (N=%d: %.3f ms)" %
+          (wall / args.steps * 1e3, np.mean(kms), nb, np.mean(kmb)), file=sys.stderr, flush=True)
     cpu, errors = None, {}
     if not args.no_cpu_baseline:
         import oracle
@@ -497,6 +510,8 @@ def bench_adjoint(args, torch, w):
         "modes": {"comp": {"value": pairs_step * args.steps / wall,
                            "adjoint_kernel_ms": float(np.mean(kms)),
                            "errors": errors.get("comp")}},
+        "adjoint_kernel_131072": {"kernel_ms": big["kernel_ms"], "frac": big["frac"],
+                                  "pairs_per_s": float(nb) * nb / (big["kernel_ms"] * 1e-3)},
     }
 
 
