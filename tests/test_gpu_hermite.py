@@ -107,3 +107,39 @@ def test_hermite_rejects_tile_centres_and_bad_arguments():
     assert _lib.nbody_hermite(64, x.data_ptr(), v.data_ptr(), m.data_ptr(), 0.01, float("nan"), 2,
                               acc.data_ptr(), jerk.data_ptr(), 0, None, None,
                               check=False) == _lib.NBODY_EINVAL
+
+
+def test_paper_scale_hermite_graph_steps():
+    """The benchmark's configuration: N = 131072, one captured Hermite step replayed
+    (dt = 1/256).  The replays equal eager steps bitwise, and after them the returned
+    acceleration and jerk (those of the last predicted state) match the oracle at that
+    state on 1024 seeded particles."""
+    w = ics.WORKLOADS["jerk_131072"]
+    x, v, m32, xd, vd, md = state(w.n, w.seed)
+    eps = float(np.float32(w.eps))
+    steps = 2
+    xe, ve = xd.clone(), vd.clone()
+    ae, je = api.hermite(xe, ve, md, eps, w.dt, steps)
+    xg, vg = xd.clone(), vd.clone()
+    ag, jg = api.hermite(xg, vg, md, eps, w.dt, 0)
+    g = api.HermiteGraph(xg, vg, md, eps, w.dt, 1, ag, jg)
+    for _ in range(steps):
+        g.launch()
+    torch.cuda.synchronize()
+    g.close()
+    assert torch.equal(xg, xe) and torch.equal(vg, ve)
+    assert torch.equal(ag, ae) and torch.equal(jg, je)
+    # Rebuild the last predicted state from the state before the last step.
+    xb, vb = xd.clone(), vd.clone()
+    ab, jb = api.hermite(xb, vb, md, eps, w.dt, steps - 1)
+    torch.cuda.synchronize()
+    dt = w.dt
+    xp = (xb + vb * dt + ab * dt * dt / 2 + jb * dt ** 3 / 6).cpu().numpy().T
+    vp = (vb + ab * dt + jb * dt * dt / 2).cpu().numpy().T
+    idx = ics.sample_indices(w.n, 1024, seed=w.seed + 1000)
+    ra, rj, _ = oracle.force_jerk(xp, vp, m32.astype(np.float64), eps, idx=idx)
+    ea = rel_errors(ae.cpu().numpy().T[idx], ra)
+    ej = rel_errors(je.cpu().numpy().T[idx], rj)
+    print("acc", ea, "jerk", ej)
+    assert ea["rel_rms"] <= 1e-6
+    assert ej["normwise"] <= 1e-5
