@@ -281,6 +281,12 @@ def bench_plummer(args, torch, w):
                       "errors": errors.get(p)} for p, r in res.items()},
         "gflops_38": pairs * 38 / (r0["kernel_ms"] * 1e-3) / 1e9,
         "gflops_20": pairs * 20 / (r0["kernel_ms"] * 1e-3) / 1e9,
+        # The paper's Table 3 at the same N on a GeForce 8800GTX (2.548 s per force call
+        # including host transfers, eps^2 = 0.01, no potential): context only, another
+        # machine and not the same workload, hence vs_baseline stays null.
+        "paper_context": {"pairs_per_s": 131072.0 ** 2 / 2.548, "gflops_38": 256.0,
+                          "ratio": pairs * args.steps / r0["wall"] / (131072.0 ** 2 / 2.548)}
+        if n == 131072 else None,
     }
 
 
