@@ -13,6 +13,7 @@
 #include <cstdlib>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "nbody_internal.h"
 
@@ -141,7 +142,12 @@ nbody_status nbody_tune_load(const char *path) {
     const size_t end = text.find(']', pos == std::string::npos ? ent : pos);
     if (pos == std::string::npos || end == std::string::npos)
         return set_error(NBODY_EINVAL, "malformed tuning file");
-    int loaded = 0;
+    // Parse and validate every entry first, so a bad file changes nothing.
+    struct Parsed {
+        int kernel, precision, bucket;
+        TuneEntry e;
+    };
+    std::vector<Parsed> entries;
     while (true) {
         const size_t ob = text.find('{', pos);
         if (ob == std::string::npos || ob > end) break;
@@ -159,13 +165,13 @@ nbody_status nbody_tune_load(const char *path) {
         const TuneEntry e{v[3], v[4], v[5]};
         if (!valid_entry(v[0], v[1], v[2], e))
             return set_error(NBODY_EINVAL, "invalid tuning entry in " + std::string(path));
-        {
-            std::lock_guard<std::mutex> lk(g_mu);
-            g_tab[v[0]][v[1]][v[2]] = e;
-            g_set[v[0]][v[1]][v[2]] = true;
-        }
-        ++loaded;
+        entries.push_back({v[0], v[1], v[2], e});
         pos = cb + 1;
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (const Parsed &p : entries) {
+        g_tab[p.kernel][p.precision][p.bucket] = p.e;
+        g_set[p.kernel][p.precision][p.bucket] = true;
     }
     return NBODY_OK;
 }

@@ -257,3 +257,18 @@ def test_tuning_rejects_bad_entries(tmp_path):
                    '"jtile": 256, "nseg": 0}]}')
     assert _lib.load().nbody_tune_load(str(bad).encode()) == _lib.NBODY_EINVAL
     assert _lib.load().nbody_tune_load(str(tmp_path / "missing.json").encode()) == _lib.NBODY_EINVAL
+
+
+def test_tuning_file_with_a_bad_entry_changes_nothing(tmp_path):
+    # A valid entry followed by an invalid one: the load fails and leaves the table as it was.
+    _lib.nbody_tune_reset()
+    before = _lib.nbody_tune_get(_lib.NBODY_KERNEL_JERK, _lib.NBODY_COMP, 4096)
+    mixed = tmp_path / "mixed.json"
+    mixed.write_text('{"entries": [{"kernel": 3, "precision": 2, "bucket": 12, "ipl": 8, '
+                     '"jtile": 512, "nseg": 7}, {"kernel": 3, "precision": 2, "bucket": 13, '
+                     '"ipl": 1, "jtile": 100, "nseg": 0}]}')
+    assert _lib.load().nbody_tune_load(str(mixed).encode()) == _lib.NBODY_EINVAL
+    assert _lib.nbody_tune_get(_lib.NBODY_KERNEL_JERK, _lib.NBODY_COMP, 4096) == before
+    _lib.nbody_tune_reset()
+    if os.path.exists(_lib.TUNING_PATH):
+        _lib.nbody_tune_load(_lib.TUNING_PATH)
