@@ -168,9 +168,10 @@ NBODY_API nbody_status nbody_force_jerk(int64_t n, const float *pos, const float
                                         double *pot, const nbody_opts *opts, void *stream);
 /* As nbody_force_jerk with FP64 state pos64, vel64 double [3][n]: the pair arithmetic
  * is FP32 on positions relative to the FP64 mean position and velocities relative to
- * the FP64 mean velocity (opts->centre = NBODY_CENTRE_SYSTEM, default) or on the
- * plain FP32 roundings (NBODY_CENTRE_NONE); NBODY_CENTRE_TILE gives
- * NBODY_EUNSUPPORTED. */
+ * the FP64 mean velocity of the system (opts->centre = NBODY_CENTRE_SYSTEM, default) or
+ * of each i-tile (NBODY_CENTRE_TILE: pays off when consecutive particles are close in
+ * phase space, e.g. after nbody_morton_order), or on the plain FP32 roundings
+ * (NBODY_CENTRE_NONE). */
 NBODY_API nbody_status nbody_force_jerk_f64(int64_t n, const double *pos64, const double *vel64,
                                             const float *mass, float eps, double *acc,
                                             double *jerk, double *pot, const nbody_opts *opts,
@@ -229,8 +230,8 @@ NBODY_API void nbody_graph_destroy(nbody_graph *graph);
  *   acc, jerk     double [3][n]: a and j at the entry state (or computed first when
  *                 flags has NBODY_LF_INIT_ACC); on return those of the last evaluation,
  *                 which the next call continues from
- *   opts          precision, centre (NONE or SYSTEM; TILE gives NBODY_EUNSUPPORTED),
- *                 ipl, jtile, nseg, workspace (nbody_workspace_size_hermite bytes)
+ *   opts          precision, centre (as nbody_force_jerk_f64), ipl, jtile, nseg,
+ *                 workspace (nbody_workspace_size_hermite bytes)
  * One force-jerk evaluation per step.  nbody_graph_create_hermite captures nsteps steps
  * (without the initial evaluation) into a graph that owns its scratch; replay it with
  * nbody_graph_launch and free it with nbody_graph_destroy. */

@@ -72,6 +72,22 @@ nbody_status jerk_f64_core(int64_t n, const double *pos64, const double *vel64, 
                            float eps, double *acc, double *jerk, double *pot, const nbody_opts &o,
                            const TileCfg &cfg, const JerkScratch &w, hipStream_t s) {
     nbody_status st;
+    if (o.centre == NBODY_CENTRE_TILE) {
+        // Per-i-tile mean positions and velocities (3 doubles per tile each, in the FP32
+        // areas this mode does not use); the pair kernel converts as it loads.
+        const int itile = kTPB * cfg.ipl;
+        double *cx = reinterpret_cast<double *>(w.x32);
+        double *cv = reinterpret_cast<double *>(w.v32);
+        if ((st = launch_tile_centres(n, itile, pos64, cx, s))) return st;
+        if ((st = launch_tile_centres(n, itile, vel64, cv, s))) return st;
+        const float e2 = eps * eps;
+        JerkTileArgs a{pos64, pos64 + n, pos64 + 2 * n, mass, vel64, vel64 + n, vel64 + 2 * n,
+                       (int)n, cfg.seg_len, e2, w.part, cfg.npad, cx, cv, itile};
+        if ((st = launch_jerk_tile(cfg, o.precision, pot != nullptr, a, s))) return st;
+        JerkFinalizeArgs fa{w.part, cfg.nseg, cfg.npad, (int)n, mass, e2, o.self_pot ? 0 : 1,
+                            acc,    jerk,     pot};
+        return launch_jerk_finalize(o.precision, fa, s);
+    }
     if (o.centre == NBODY_CENTRE_SYSTEM) {
         // Positions relative to the FP64 mean position, velocities relative to the FP64
         // mean velocity: differences of the shifted values are what the pairs need.
@@ -115,8 +131,6 @@ nbody_status check_hermite(int64_t n, const double *x, const double *v, const fl
     if (st) return st;
     if (nsteps < 0) return set_error(NBODY_EINVAL, "nsteps must be >= 0");
     if (!std::isfinite(dt)) return set_error(NBODY_EINVAL, "dt must be finite");
-    if (o.centre == NBODY_CENTRE_TILE)
-        return set_error(NBODY_EUNSUPPORTED, "the Hermite path supports NBODY_CENTRE_NONE and _SYSTEM");
     if (misaligned(x) || misaligned(v) || misaligned(m) || misaligned(acc) || misaligned(jerk))
         return set_error(NBODY_EINVAL, "misaligned array argument");
     return NBODY_OK;
@@ -181,8 +195,6 @@ nbody_status nbody_force_jerk_f64(int64_t n, const double *pos64, const double *
     nbody_opts o = resolve_opts(opts);
     nbody_status st = check_jerk(n, pos64, vel64, mass, eps, acc, jerk, o);
     if (st) return st;
-    if (o.centre == NBODY_CENTRE_TILE)
-        return set_error(NBODY_EUNSUPPORTED, "the jerk path supports NBODY_CENTRE_NONE and _SYSTEM");
     if (misaligned(pos64) || misaligned(vel64) || misaligned(mass) || misaligned(acc) ||
         misaligned(jerk) || misaligned(pot))
         return set_error(NBODY_EINVAL, "misaligned array argument");

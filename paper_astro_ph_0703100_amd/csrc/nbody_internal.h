@@ -90,6 +90,22 @@ struct JerkArgs {
     int npad;
 };
 
+// The same on FP64 state taken relative to per-i-tile FP64 centres of position and
+// velocity (converted to FP32 by each block as it loads its i's and stages its j's).
+struct JerkTileArgs {
+    const double *x, *y, *z;     // FP64 positions [3][n]
+    const float *m;
+    const double *vx, *vy, *vz;  // FP64 velocities [3][n]
+    int n;
+    int seg_len;
+    float eps2;
+    void *part;
+    int npad;
+    const double *cx;            // [i-tiles][3] mean position of each i-tile
+    const double *cv;            // [i-tiles][3] mean velocity of each i-tile
+    int itile;                   // particles per i-tile (256 * IPL)
+};
+
 struct JerkFinalizeArgs {
     const void *part;
     int nseg, npad, n;
@@ -279,6 +295,8 @@ nbody_status launch_batched_convert(int64_t total, const double *pos64, const in
 nbody_status launch_jerk(const TileCfg &cfg, int precision, bool with_pot, const JerkArgs &a,
                          hipStream_t s);
 nbody_status launch_jerk_finalize(int precision, const JerkFinalizeArgs &a, hipStream_t s);
+nbody_status launch_jerk_tile(const TileCfg &cfg, int precision, bool with_pot,
+                              const JerkTileArgs &a, hipStream_t s);
 // Fourth-order Hermite predictor and corrector (hermite.hip).
 nbody_status launch_hermite_predict(int64_t n, const double *x, const double *v, const double *a,
                                     const double *j, double dt, double *xp, double *vp,

@@ -107,9 +107,9 @@ def test_force_jerk_rejects_invalid_arguments(entry, args, what):
 
 def test_force_jerk_options():
     o = _lib.nbody_opts_default()
-    o.centre = _lib.NBODY_CENTRE_TILE
+    o.centre = 7
     assert _lib.nbody_force_jerk_f64(10, FAKE, FAKE, FAKE, 0.1, FAKE, FAKE, None, o, None,
-                                     check=False) == _lib.NBODY_EUNSUPPORTED
+                                     check=False) == _lib.NBODY_EINVAL
     assert _lib.nbody_force_jerk(0, None, None, None, 0.1, None, None, None, None, None,
                                  check=False) == _lib.NBODY_OK
 

@@ -98,13 +98,33 @@ def test_graph_replays_equal_eager():
     assert torch.equal(ag, ae) and torch.equal(jg, je)
 
 
-def test_hermite_rejects_tile_centres_and_bad_arguments():
-    _, _, _, x, v, m = state(64, 77)
-    acc = torch.empty_like(x)
-    jerk = torch.empty_like(x)
-    with pytest.raises(_lib.NBodyError):
-        api.hermite(x, v, m, 0.01, 0.01, 2, acc=acc, jerk=jerk, centre="tile")
-    assert _lib.nbody_hermite(64, x.data_ptr(), v.data_ptr(), m.data_ptr(), 0.01, float("nan"), 2,
+def test_hermite_with_tile_centres_and_bad_arguments():
+    # Morton-sorted system far from the origin: per-i-tile centres of position and
+    # velocity; the trajectory matches the oracle like the system-centre path.
+    n, dt, steps = 2000, 1.0 / 256, 8
+    eps = float(np.float32(0.02))
+    x, v, m = ics.plummer(n, seed=79)
+    x = x + np.array([500.0, 20.0, -30.0])
+    v = v + np.array([-10.0, 5.0, 0.0])
+    xt = torch.from_numpy(np.ascontiguousarray(x.T)).to(DEV)
+    perm = api.morton_order(xt).cpu().numpy().astype(np.int64)
+    x, v, m32 = x[perm], v[perm], m[perm].astype(np.float32)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a.T)).to(DEV)
+    xd, vd, md = t(x), t(v), torch.from_numpy(m32).to(DEV)
+    m64 = m32.astype(np.float64)
+    da = force_error(xd, vd, md, x, v, m64, eps, "comp")
+    acc, jerk = api.hermite(xd, vd, md, eps, dt, steps, centre="tile")
+    torch.cuda.synchronize()
+    xo, vo, ao, jo = oracle.hermite(x, v, m64, eps, dt, steps)
+    T = dt * steps
+    dx = np.abs(xd.cpu().numpy().T - xo).max()
+    dv = np.abs(vd.cpu().numpy().T - vo).max()
+    print("tile centres: dx %.2e dv %.2e (system-centre force error %.2e)" % (dx, dv, da))
+    assert dx <= 10 * T * T * da and dv <= 10 * T * da
+    assert rel_errors(acc.cpu().numpy().T, ao)["rel_rms"] < 1e-6
+    acc = torch.empty_like(xd)
+    jerk = torch.empty_like(xd)
+    assert _lib.nbody_hermite(n, xd.data_ptr(), vd.data_ptr(), md.data_ptr(), 0.01, float("nan"), 2,
                               acc.data_ptr(), jerk.data_ptr(), 0, None, None,
                               check=False) == _lib.NBODY_EINVAL
 
