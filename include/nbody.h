@@ -62,16 +62,16 @@ typedef int32_t nbody_status;
 #define NBODY_COMP 2    /* FP32 partial over each block of j, added into an FP32
                            (hi, lo) pair by an error-free two-sum; default              */
 
-/* Reference centre for FP64 positions (nbody_force_f64 and the leapfrog). */
+/* Reference centre for FP64 positions (every *_f64 entry point, the leapfrog, its
+ * adjoint and the Hermite integrator). */
 #define NBODY_CENTRE_NONE 0   /* pair arithmetic on fp32(x)                              */
 #define NBODY_CENTRE_SYSTEM 1 /* on fp32(x - c), c = FP64 mean position of the system;
                                  default                                                 */
 #define NBODY_CENTRE_TILE 2   /* on fp32(x - c_I), c_I = FP64 mean of the i-tile (256 x
                                  ipl consecutive particles), j's converted for each i-tile
                                  as they are staged; pays off when consecutive particles
-                                 are spatially close (see nbody_morton_order).  Force and
-                                 leapfrog only (the adjoint and batched plans return
-                                 NBODY_EUNSUPPORTED).                                    */
+                                 are spatially close (see nbody_morton_order).  Batched
+                                 plans return NBODY_EUNSUPPORTED.                        */
 
 typedef struct nbody_opts {
     int32_t precision;  /* NBODY_PLAIN, NBODY_FP64RED or NBODY_COMP                   */

@@ -17,8 +17,6 @@ nbody_status check_vjp(int64_t n, const void *pos, const float *mass, float eps,
     if (misaligned(mass) || misaligned(g_acc) || misaligned(g_pot) || misaligned(grad_pos) ||
         misaligned(grad_mass))
         return set_error(NBODY_EINVAL, "misaligned array argument");
-    if (o.centre == NBODY_CENTRE_TILE)
-        return set_error(NBODY_EUNSUPPORTED, "the adjoint supports NBODY_CENTRE_NONE and _SYSTEM");
     return NBODY_OK;
 }
 
@@ -47,6 +45,19 @@ nbody_status vjp_f64_core(int64_t n, const double *pos64, const float *mass, flo
                           double *grad_mass, bool accumulate, const nbody_opts &o,
                           const TileCfg &cfg, const F64Scratch &ws, hipStream_t s) {
     nbody_status st;
+    if (o.centre == NBODY_CENTRE_TILE) {
+        // Per-i-tile centres in the FP32-position area (unused in this mode).
+        const int itile = kTPB * cfg.ipl;
+        double *centres = reinterpret_cast<double *>(ws.x32);
+        if ((st = launch_tile_centres(n, itile, pos64, centres, s))) return st;
+        const float e2 = eps * eps;
+        VjpTileArgs va{pos64, pos64 + n, pos64 + 2 * n, mass, g_acc, g_acc + n, g_acc + 2 * n,
+                       g_pot, (int)n, cfg.seg_len, e2, ws.part, cfg.npad, centres, itile};
+        if ((st = launch_vjp_tile(cfg, o.precision, va, grad_mass != nullptr, s))) return st;
+        VjpFinalizeArgs fa{ws.part, cfg.nseg, cfg.npad, (int)n, g_pot, e2, grad_pos, grad_mass,
+                           accumulate ? 1 : 0};
+        return launch_vjp_finalize(o.precision, fa, s);
+    }
     if (o.centre == NBODY_CENTRE_SYSTEM) {
         if ((st = launch_centre(n, pos64, ws.centre, ws.centre_scratch, s))) return st;
         if ((st = launch_convert(n, pos64, ws.centre, ws.x32, s))) return st;
@@ -112,8 +123,6 @@ nbody_status nbody_leapfrog_adjoint(int64_t n, const double *traj, const float *
     if (misaligned(traj) || misaligned(mass) || misaligned(xbar) || misaligned(vbar) ||
         misaligned(mbar))
         return set_error(NBODY_EINVAL, "misaligned array argument");
-    if (o.centre == NBODY_CENTRE_TILE)
-        return set_error(NBODY_EUNSUPPORTED, "the adjoint supports NBODY_CENTRE_NONE and _SYSTEM");
     if (n == 0) return NBODY_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
     TileCfg cfg;

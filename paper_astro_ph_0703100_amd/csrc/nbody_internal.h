@@ -181,6 +181,21 @@ struct VjpArgs {
     int npad;
 };
 
+// The adjoint on FP64 positions relative to per-i-tile FP64 centres.
+struct VjpTileArgs {
+    const double *x, *y, *z;         // FP64 positions [3][n]
+    const float *m;
+    const double *gx, *gy, *gz;      // dL/da [3][n]
+    const double *gp;                // dL/dphi [n] or nullptr
+    int n;
+    int seg_len;
+    float eps2;
+    void *part;
+    int npad;
+    const double *centres;           // [i-tiles][3] mean position of each i-tile
+    int itile;
+};
+
 struct VjpFinalizeArgs {
     const void *part;
     int nseg, npad, n;
@@ -306,6 +321,8 @@ nbody_status launch_hermite_correct(int64_t n, double *x, double *v, double *a, 
 // Adjoint pair kernel and its FP64 finalize (vjp.hip).
 nbody_status launch_vjp(const TileCfg &cfg, int precision, const VjpArgs &a, bool with_mass,
                         hipStream_t s);
+nbody_status launch_vjp_tile(const TileCfg &cfg, int precision, const VjpTileArgs &a,
+                             bool with_mass, hipStream_t s);
 nbody_status launch_vjp_finalize(int precision, const VjpFinalizeArgs &a, hipStream_t s);
 
 }  // namespace nbody

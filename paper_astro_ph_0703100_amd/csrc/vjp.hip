@@ -99,6 +99,46 @@ struct Adjoint {
     }
 };
 
+// The same on FP64 positions relative to the block's i-tile centre: i's and staged j's
+// are converted as fp32(x - c_I) while loaded (for j == k the two conversions are the
+// same operation, so d = 0 exactly).
+struct AdjointTile {
+    static constexpr int kJWords = 8;
+    static constexpr int kOut = 4;
+    static constexpr int kBlockJ = Adjoint::kBlockJ;
+    using Args = VjpTileArgs;
+    using IState = Adjoint::IState;
+    struct Ctx {
+        double cx, cy, cz;
+    };
+    static __device__ __forceinline__ int n_i(const Args &a) { return a.n; }
+    static __device__ __forceinline__ int n_j(const Args &a) { return a.n; }
+    static __device__ __forceinline__ Ctx make_ctx(const Args &a, int i0) {
+        const double *c = a.centres + 3 * (size_t)(i0 / a.itile);
+        return {c[0], c[1], c[2]};
+    }
+    static __device__ __forceinline__ IState load_i(const Args &a, const Ctx &c, int i) {
+        return {(float)(a.x[i] - c.cx), (float)(a.y[i] - c.cy), (float)(a.z[i] - c.cz), a.m[i],
+                (float)a.gx[i], (float)a.gy[i], (float)a.gz[i], a.gp ? (float)a.gp[i] : 0.0f};
+    }
+    static __device__ __forceinline__ void load_j(const Args &a, const Ctx &c, int j, float (&r)[8]) {
+        r[0] = (float)(a.x[j] - c.cx);
+        r[1] = (float)(a.y[j] - c.cy);
+        r[2] = (float)(a.z[j] - c.cz);
+        r[3] = a.m[j];
+        r[4] = (float)a.gx[j];
+        r[5] = (float)a.gy[j];
+        r[6] = (float)a.gz[j];
+        r[7] = a.gp ? (float)a.gp[j] : 0.0f;
+    }
+    static __device__ __forceinline__ void pad_j(float (&r)[8]) { Adjoint::pad_j(r); }
+    template <bool MASS>
+    static __device__ __forceinline__ void pair(const float *j, const IState &k, float eps2,
+                                                float (&acc)[4]) {
+        Adjoint::pair<MASS>(j, k, eps2, acc);
+    }
+};
+
 template <int MODE>
 __global__ __launch_bounds__(256) void vjp_finalize_kernel(VjpFinalizeArgs a) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -130,6 +170,16 @@ nbody_status launch_vjp(const TileCfg &cfg, int precision, const VjpArgs &a, boo
                         hipStream_t s) {
     auto fn = engine::pick_tile<Adjoint>(cfg.ipl, cfg.jt, precision, with_mass);
     if (!fn) return set_error(NBODY_EUNSUPPORTED, "no VJP kernel for this ipl/jtile/precision");
+    if (cfg.itiles <= 0 || cfg.nseg <= 0) return NBODY_OK;
+    hipLaunchKernelGGL(fn, dim3(cfg.itiles, cfg.nseg), dim3(kTPB), 0, s, a);
+    NBODY_HIP_CHECK(hipGetLastError());
+    return NBODY_OK;
+}
+
+nbody_status launch_vjp_tile(const TileCfg &cfg, int precision, const VjpTileArgs &a,
+                             bool with_mass, hipStream_t s) {
+    auto fn = engine::pick_tile<AdjointTile>(cfg.ipl, cfg.jt, precision, with_mass);
+    if (!fn) return set_error(NBODY_EUNSUPPORTED, "no tile-centre VJP kernel for this shape");
     if (cfg.itiles <= 0 || cfg.nseg <= 0) return NBODY_OK;
     hipLaunchKernelGGL(fn, dim3(cfg.itiles, cfg.nseg), dim3(kTPB), 0, s, a);
     NBODY_HIP_CHECK(hipGetLastError());

@@ -215,3 +215,54 @@ def test_rollout_gradient_adjoint_16384():
     print("loss", loss, lo, "grad x0", ex, "v0", ev, "m", em)
     assert abs(loss - lo) <= 1e-6 * abs(lo)
     assert ex["normwise"] <= 1e-4 and ev["normwise"] <= 1e-4 and em["normwise"] <= 1e-4
+
+
+@pytest.mark.parametrize("centre", ["tile", "system"])
+def test_vjp_f64_centres_far_from_origin(centre):
+    # FP64 positions offset to (300, 0, -40) and Morton-sorted: the adjoint on positions
+    # relative to per-i-tile or per-system FP64 centres matches the oracle VJP on the FP64
+    # positions.
+    n = 3000
+    pos, _, mass = ics.plummer(n, seed=34, velocities=False)
+    pos = pos + np.array([300.0, 0.0, -40.0])
+    x = torch.from_numpy(np.ascontiguousarray(pos.T)).to(DEV)
+    perm = api.morton_order(x).cpu().numpy().astype(np.int64)
+    pos = pos[perm]
+    m32 = (mass * np.random.default_rng(35).uniform(0.5, 1.5, n)).astype(np.float32)[perm]
+    rng = np.random.default_rng(36)
+    ga, gp = rng.standard_normal((n, 3)), rng.standard_normal(n)
+    eps = float(np.float32(0.02))
+    x = torch.from_numpy(np.ascontiguousarray(pos.T)).to(DEV)
+    m = torch.from_numpy(m32).to(DEV)
+    g = torch.from_numpy(np.ascontiguousarray(ga.T)).to(DEV)
+    gpt = torch.from_numpy(gp).to(DEV)
+    gx = torch.empty((3, n), dtype=torch.float64, device=DEV)
+    gm = torch.empty(n, dtype=torch.float64, device=DEV)
+    _lib.nbody_force_vjp_f64(n, x.data_ptr(), m.data_ptr(), eps, g.data_ptr(), gpt.data_ptr(),
+                             gx.data_ptr(), gm.data_ptr(), api.make_opts(centre=centre),
+                             api.stream_ptr())
+    torch.cuda.synchronize()
+    rx, rm = oracle.vjp(pos, m32.astype(np.float64), eps, ga.astype(np.float32).astype(np.float64),
+                        gp.astype(np.float32).astype(np.float64))
+    ex, em = rel_errors(gx.cpu().numpy().T, rx), rel_errors(gm.cpu().numpy(), rm)
+    print(centre, "grad_pos", ex, "grad_mass", em)
+    assert ex["normwise"] <= 1e-5 and em["normwise"] <= 1e-5
+
+
+def test_rollout_gradient_with_tile_centres():
+    n, steps, dt, eps = 64, 32, 1.0 / 256, float(np.float32(0.05))
+    x0, v0, mass = ics.plummer(n, seed=80)
+    m32 = mass.astype(np.float32).astype(np.float64)
+    y = ics.perturbed_target(x0, seed=81)
+    lo, rx, rv, rm = oracle.rollout_loss_grad(x0, v0, m32, eps, dt, steps, y)
+    xt = torch.from_numpy(np.ascontiguousarray(x0.T)).to(DEV).requires_grad_(True)
+    vt = torch.from_numpy(np.ascontiguousarray(v0.T)).to(DEV).requires_grad_(True)
+    mt = torch.from_numpy(m32).to(DEV).requires_grad_(True)
+    yt = torch.from_numpy(np.ascontiguousarray(y.T)).to(DEV)
+    xT, _ = autograd.rollout(xt, vt, mt, eps, dt, steps, centre="tile")
+    loss = ((xT - yt) ** 2).sum() / n
+    loss.backward()
+    assert abs(float(loss.detach()) - lo) <= 1e-6 * abs(lo)
+    for a, b in ((xt.grad.cpu().numpy().T, rx), (vt.grad.cpu().numpy().T, rv),
+                 (mt.grad.cpu().numpy(), rm)):
+        assert rel_errors(a, b)["normwise"] <= 1e-5
