@@ -59,8 +59,7 @@ nbody_status vjp_f64_core(int64_t n, const double *pos64, const float *mass, flo
         return launch_vjp_finalize(o.precision, fa, s);
     }
     if (o.centre == NBODY_CENTRE_SYSTEM) {
-        if ((st = launch_centre(n, pos64, ws.centre, ws.centre_scratch, s))) return st;
-        if ((st = launch_convert(n, pos64, ws.centre, ws.x32, s))) return st;
+        if ((st = launch_centred_convert(n, pos64, ws.centre_scratch, ws.x32, s))) return st;
     } else {
         if ((st = launch_convert(n, pos64, nullptr, ws.x32, s))) return st;
     }
@@ -135,15 +134,19 @@ nbody_status nbody_leapfrog_adjoint(int64_t n, const double *traj, const float *
     double *abar = reinterpret_cast<double *>(static_cast<char *>(ws) + base);
     const double h = 0.5 * dt;
 
-    // abar holds the cotangent of a(x_t) summed over the two kicks that use it.
+    // abar holds the cotangent of a(x_t) summed over the two kicks that use it: the
+    // second kick of step t - 1 and the first kick of step t both scale a(x_t) by h and
+    // see the same vbar (nothing changes v between them), so together they give
+    // abar = dt vbar; the last state's a is used by one kick only.
     if ((st = launch_fill_f64((int64_t)n3, abar, 0.0, s))) return st;
+    if ((st = launch_axpy_f64((int64_t)n3, abar, h, vbar, s))) return st;
     for (int32_t t = nsteps - 1; t >= 0; --t) {
         const double *x1 = traj + (size_t)(t + 1) * n3;
-        if ((st = launch_axpy_f64((int64_t)n3, abar, h, vbar, s))) return st;  // second kick
         if ((st = vjp_f64_core(n, x1, mass, eps, abar, nullptr, xbar, mbar, true, o, cfg, lay, s)))
             return st;
-        // drift (vbar += dt xbar) and first kick of step t (abar = h vbar)
-        if ((st = launch_adj_drift_kick((int64_t)n3, vbar, xbar, abar, dt, h, s))) return st;
+        // drift of step t (vbar += dt xbar), then both kicks that use a(x_t)
+        if ((st = launch_adj_drift_kick((int64_t)n3, vbar, xbar, abar, dt, t > 0 ? dt : h, s)))
+            return st;
     }
     return vjp_f64_core(n, traj, mass, eps, abar, nullptr, xbar, mbar, true, o, cfg, lay, s);
 }

@@ -183,7 +183,7 @@ nbody_status check_common(int64_t n, const void *pos, const void *mass, float ep
 
 size_t f64_scratch_bytes(int64_t n, const TileCfg &cfg, int precision) {
     return partial_bytes(cfg, precision) + align_up(sizeof(float) * 3 * (size_t)n, 256) +
-           align_up(centre_scratch_bytes() + 4 * sizeof(double), 256);
+           align_up(centre_scratch_bytes(), 256);
 }
 
 F64Scratch f64_scratch_layout(void *ws, int64_t n, const TileCfg &cfg, int precision) {
@@ -193,8 +193,7 @@ F64Scratch f64_scratch_layout(void *ws, int64_t n, const TileCfg &cfg, int preci
     F64Scratch r;
     r.part = base;
     r.x32 = reinterpret_cast<float *>(base + pb);
-    r.centre = reinterpret_cast<double *>(base + pb + xb);
-    r.centre_scratch = r.centre + 4;
+    r.centre_scratch = reinterpret_cast<double *>(base + pb + xb);
     return r;
 }
 
@@ -234,8 +233,7 @@ nbody_status force_f64_core(int64_t n, const double *pos64, const float *mass, f
         return launch_finalize(o.precision, fa, s);
     }
     if (o.centre == NBODY_CENTRE_SYSTEM) {
-        if ((st = launch_centre(n, pos64, ws.centre, ws.centre_scratch, s))) return st;
-        if ((st = launch_convert(n, pos64, ws.centre, ws.x32, s))) return st;
+        if ((st = launch_centred_convert(n, pos64, ws.centre_scratch, ws.x32, s))) return st;
     } else {
         if ((st = launch_convert(n, pos64, nullptr, ws.x32, s))) return st;
     }

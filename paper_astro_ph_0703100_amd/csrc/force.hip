@@ -34,7 +34,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinalizeArgs a) {
 }
 
 // Two-stage fixed-order FP64 mean of the positions [3][n]: kCentreBlocks partial
-// sums, then one block adds them.  Deterministic for a given n.
+// sums, then their fixed-order sum.  Deterministic for a given n.
 constexpr int kCentreBlocks = 256;
 
 __global__ __launch_bounds__(256) void centre_partial_kernel(int64_t n, const double *pos,
@@ -56,8 +56,11 @@ __global__ __launch_bounds__(256) void centre_partial_kernel(int64_t n, const do
     if (threadIdx.x < 3) part[blockIdx.x * 3 + threadIdx.x] = sh[threadIdx.x][0];
 }
 
-__global__ __launch_bounds__(256) void centre_final_kernel(int64_t n, const double *part,
-                                                          double *centre) {
+// The second stage fused with the conversion to FP32: every block adds the
+// kCentreBlocks partials in the same fixed tree order, so all blocks use the identical
+// centre c = sum / n, then converts its 256 particles to fp32(x - c).
+__global__ __launch_bounds__(256) void centred_convert_kernel(int64_t n, const double *pos,
+                                                             const double *part, float *out) {
     __shared__ double sh[3][kCentreBlocks];
 #pragma unroll
     for (int c = 0; c < 3; ++c) sh[c][threadIdx.x] = part[threadIdx.x * 3 + c];
@@ -68,7 +71,10 @@ __global__ __launch_bounds__(256) void centre_final_kernel(int64_t n, const doub
             for (int c = 0; c < 3; ++c) sh[c][threadIdx.x] += sh[c][threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x < 3) centre[threadIdx.x] = n > 0 ? sh[threadIdx.x][0] / (double)n : 0.0;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) out[c * n + i] = (float)(pos[c * n + i] - sh[c][0] / (double)n);
 }
 
 __global__ __launch_bounds__(256) void convert_kernel(int64_t n, const double *pos,
@@ -149,12 +155,13 @@ nbody_status launch_finalize(int precision, const FinalizeArgs &a, hipStream_t s
 
 size_t centre_scratch_bytes() { return sizeof(double) * 3 * kCentreBlocks; }
 
-nbody_status launch_centre(int64_t n, const double *pos64, double *centre, double *scratch,
-                           hipStream_t s) {
+nbody_status launch_centred_convert(int64_t n, const double *pos64, double *scratch,
+                                    float *pos32, hipStream_t s) {
+    if (n <= 0) return NBODY_OK;
     hipLaunchKernelGGL(centre_partial_kernel, dim3(kCentreBlocks), dim3(256), 0, s, n, pos64, scratch);
     NBODY_HIP_CHECK(hipGetLastError());
-    hipLaunchKernelGGL(centre_final_kernel, dim3(1), dim3(kCentreBlocks), 0, s, n,
-                       (const double *)scratch, centre);
+    hipLaunchKernelGGL(centred_convert_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                       n, pos64, (const double *)scratch, pos32);
     NBODY_HIP_CHECK(hipGetLastError());
     return NBODY_OK;
 }

@@ -18,17 +18,18 @@ size_t jerk_partial_bytes(const TileCfg &c, int precision) {
     return align_up((size_t)c.nseg * words * (size_t)c.npad * 4, 256);
 }
 
-// FP64-state scratch: partial sums, FP32 relative positions and velocities [3][n] each,
-// the two FP64 centres (4 doubles each) and the centre-reduction partials.
+// FP64-state scratch: partial sums, FP32 relative positions and velocities [3][n] each
+// (or, with per-i-tile centres, the tile centres of each), and the partials of the
+// system-mean reductions.
 struct JerkScratch {
     void *part;
     float *x32, *v32;
-    double *cx, *cv, *cscratch;
+    double *cscratch;
 };
 
 size_t jerk_f64_bytes(int64_t n, const TileCfg &c, int precision) {
     return jerk_partial_bytes(c, precision) + 2 * align_up(sizeof(float) * 3 * (size_t)n, 256) +
-           align_up(centre_scratch_bytes() + 8 * sizeof(double), 256);
+           align_up(centre_scratch_bytes(), 256);
 }
 
 JerkScratch jerk_f64_layout(void *ws, int64_t n, const TileCfg &c, int precision) {
@@ -39,9 +40,7 @@ JerkScratch jerk_f64_layout(void *ws, int64_t n, const TileCfg &c, int precision
     r.part = b;
     r.x32 = reinterpret_cast<float *>(b + pb);
     r.v32 = reinterpret_cast<float *>(b + pb + xb);
-    r.cx = reinterpret_cast<double *>(b + pb + 2 * xb);
-    r.cv = r.cx + 4;
-    r.cscratch = r.cv + 4;
+    r.cscratch = reinterpret_cast<double *>(b + pb + 2 * xb);
     return r;
 }
 
@@ -91,10 +90,8 @@ nbody_status jerk_f64_core(int64_t n, const double *pos64, const double *vel64, 
     if (o.centre == NBODY_CENTRE_SYSTEM) {
         // Positions relative to the FP64 mean position, velocities relative to the FP64
         // mean velocity: differences of the shifted values are what the pairs need.
-        if ((st = launch_centre(n, pos64, w.cx, w.cscratch, s))) return st;
-        if ((st = launch_convert(n, pos64, w.cx, w.x32, s))) return st;
-        if ((st = launch_centre(n, vel64, w.cv, w.cscratch, s))) return st;
-        if ((st = launch_convert(n, vel64, w.cv, w.v32, s))) return st;
+        if ((st = launch_centred_convert(n, pos64, w.cscratch, w.x32, s))) return st;
+        if ((st = launch_centred_convert(n, vel64, w.cscratch, w.v32, s))) return st;
     } else {
         if ((st = launch_convert(n, pos64, nullptr, w.x32, s))) return st;
         if ((st = launch_convert(n, vel64, nullptr, w.v32, s))) return st;

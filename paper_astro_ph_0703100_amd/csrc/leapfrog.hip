@@ -5,16 +5,19 @@
 namespace nbody {
 namespace {
 
-// First half-kick fused with the drift: v += h a; x += dt v.
+// First half-kick fused with the drift: v += h a; x += dt v; the new x also goes to
+// `checkpoint` when that is not null (the rollout's stored trajectory).
 __global__ __launch_bounds__(256) void kick_drift_kernel(int64_t count, double *__restrict__ x,
                                                         double *__restrict__ v,
                                                         const double *__restrict__ a, double h,
-                                                        double dt) {
+                                                        double dt, double *__restrict__ checkpoint) {
     const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (q >= count) return;
     const double vv = v[q] + h * a[q];
     v[q] = vv;
-    x[q] = x[q] + dt * vv;
+    const double xx = x[q] + dt * vv;
+    x[q] = xx;
+    if (checkpoint) checkpoint[q] = xx;
 }
 
 __global__ __launch_bounds__(256) void kick_kernel(int64_t count, double *__restrict__ v,
@@ -61,9 +64,10 @@ dim3 grid_for(int64_t count) { return dim3((unsigned)((count + 255) / 256)); }
 }  // namespace
 
 nbody_status launch_kick_drift(int64_t n, double *x, double *v, const double *acc, double h,
-                               double dt, hipStream_t s) {
+                               double dt, hipStream_t s, double *checkpoint) {
     if (n <= 0) return NBODY_OK;
-    hipLaunchKernelGGL(kick_drift_kernel, grid_for(3 * n), dim3(256), 0, s, 3 * n, x, v, acc, h, dt);
+    hipLaunchKernelGGL(kick_drift_kernel, grid_for(3 * n), dim3(256), 0, s, 3 * n, x, v, acc, h, dt,
+                       checkpoint);
     NBODY_HIP_CHECK(hipGetLastError());
     return NBODY_OK;
 }

@@ -237,11 +237,11 @@ nbody_status check_common(int64_t n, const void *pos, const void *mass, float ep
 nbody_opts resolve_opts(const nbody_opts *opts);
 
 // Scratch layout of one FP64-position force evaluation: partial sums, FP32 relative
-// positions [3][n], reference centre (4 doubles) and the centre-reduction partials.
+// positions [3][n] (or, with per-i-tile centres, the tile centres), and the partials of
+// the system-centre reduction.
 struct F64Scratch {
     void *part;
     float *x32;
-    double *centre;
     double *centre_scratch;
 };
 size_t f64_scratch_bytes(int64_t n, const TileCfg &cfg, int precision);
@@ -270,8 +270,10 @@ nbody_status launch_pair(const TileCfg &cfg, int precision, bool with_pot, const
 nbody_status launch_finalize(int precision, const FinalizeArgs &a, hipStream_t s);
 nbody_status launch_pair_ij(const TileCfg &cfg, int precision, bool with_pot, const IJPairArgs &a,
                             hipStream_t s);
-nbody_status launch_centre(int64_t n, const double *pos64, double *centre, double *scratch,
-                           hipStream_t s);
+// fp32(x - c) with c the FP64 mean of all positions (two kernels: block partial sums,
+// then a fused fixed-order final sum and conversion); scratch holds the partials.
+nbody_status launch_centred_convert(int64_t n, const double *pos64, double *scratch,
+                                    float *pos32, hipStream_t s);
 nbody_status launch_convert(int64_t n, const double *pos64, const double *centre, float *pos32,
                             hipStream_t s);
 // Bytes of the centre-reduction scratch (partials of the two-stage FP64 sum).
@@ -287,8 +289,9 @@ nbody_status launch_morton_order(int64_t n, const double *pos64, int32_t *perm, 
                                  hipStream_t s);
 size_t morton_scratch_bytes(int64_t n);
 // Leapfrog pieces (leapfrog.hip).
+// v += h a; x += dt v (and checkpoint = x when checkpoint is not null).
 nbody_status launch_kick_drift(int64_t n, double *x, double *v, const double *acc, double h,
-                               double dt, hipStream_t s);
+                               double dt, hipStream_t s, double *checkpoint = nullptr);
 nbody_status launch_kick(int64_t n, double *v, const double *acc, double h, hipStream_t s);
 nbody_status launch_copy_f64(int64_t count, const double *src, double *dst, hipStream_t s);
 nbody_status launch_fill_f64(int64_t count, double *dst, double value, hipStream_t s);
