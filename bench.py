@@ -84,11 +84,21 @@ def peak_pairs(kind: str) -> float:
     return LANE_ISSUE / SLOTS[kind]
 
 
+_TOKEN = re.compile(r'"(?:\\.|[^"\\\n])*"|\'(?:\\.|[^\'\\\n])*\'|//[^\n]*|/\*.*?\*/', re.S)
+
+
+def code_text(src: str) -> str:
+    """C++ source with its comments removed and its whitespace collapsed: what a change to
+    the kernel's code changes, and a change to its comments does not."""
+    code = _TOKEN.sub(lambda t: t.group(0) if t.group(0)[0] in "\"'" else " ", src)
+    return " ".join(code.split())
+
+
 def sources_hash() -> str:
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, rel)) as f:
+            h.update(code_text(f.read()).encode())
     with open(os.path.join(ROOT, TUNING_FILE)) as f:
         force = [e for e in json.load(f)["entries"]
                  if e.get("kernel") == 0 and e.get("bucket") == 17]

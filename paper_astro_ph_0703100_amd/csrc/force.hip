@@ -9,7 +9,9 @@ namespace {
 // one thread per (particle, output) so that few particles with many segments still
 // fill the chip; then removal of the j == i potential term fl(m_i * rsq(eps^2)),
 // recomputed with the FP32 operations the pair body used for it (exact removal; the
-// rounding that term caused while it was in the sums is at most about u * m_i / eps).
+// rounding that term caused while it was in an FP32 partial is at most about
+// A * u * (m_i / eps + |phi_i|), A the FP32 additions that followed it: fewer than one
+// block in the FP64 and compensated modes).
 // With kick_v set, the velocity kick of a leapfrog step follows in FP64.
 // Grid: (ceil(n / 256), 4 outputs, or 3 without potentials).
 template <int MODE>

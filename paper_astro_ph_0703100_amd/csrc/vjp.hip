@@ -11,7 +11,8 @@
 // For j == k, d = 0 exactly and w is the difference of two identically rounded
 // products (no FMA contraction), so that pair adds exactly zero to dL/dx_k; its term
 // fl(p_k rsq(eps^2)) in dL/dm_k is rounded on its own and removed exactly in the FP64
-// finalize (the rounding it caused inside the sums is at most about u |p_k| / eps).
+// finalize (the rounding it caused inside an FP32 block partial is at most about
+// kBlockJ u (|p_k| / eps + sum_j |p_j| / s)).
 // 38 VALU operations and one v_rsq_f32 per pair.
 #include "tile_engine.h"
 

@@ -41,3 +41,10 @@ def test_committed_traffic_matches_the_current_sources():
         assert bench.committed_traffic() == rec["bytes_per_launch"]
     else:
         assert bench.committed_traffic() is None
+
+
+def test_sources_hash_ignores_comments_only():
+    src = 'x = a / b; // u m / eps\n/* block\n comment */ s = "//kept"; c = \'/\';\n'
+    assert bench.code_text(src) == bench.code_text(src.replace("u m / eps", "A u (m / eps)"))
+    assert bench.code_text(src) != bench.code_text(src.replace("a / b", "a * b"))
+    assert '"//kept"' in bench.code_text(src)

@@ -1,0 +1,108 @@
+"""Seeded random launch shapes and sizes for every pair pipeline against the oracle.
+
+Each case draws a particle count (ragged against every tile size), a launch shape
+(i-particles per lane, j-tile, j-segments, including more segments than j-tiles), an
+accumulation mode and a softening, and compares the GPU result with the FP64 oracle on
+the same FP32 values.  Tolerances as elsewhere: compensated and FP64-reduced relative
+RMS <= 1e-6 for accelerations, plain FP32 <= 1e-5; the potential within the self-term
+rounding bound derived in ``test_force``.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_astro_ph_0703100_amd import api, ics
+from paper_astro_ph_0703100_amd.metrics import rel_errors
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+U = 2.0 ** -24
+TOL = {"comp": 1e-6, "fp64red": 1e-6, "plain": 1e-5}
+
+
+def draw(rng):
+    return {"n": int(rng.integers(2, 5000)), "ipl": int(rng.choice([1, 2, 4, 8])),
+            "jtile": int(rng.choice([64, 128, 256, 512])), "nseg": int(rng.integers(0, 70)),
+            "precision": str(rng.choice(["comp", "fp64red", "plain"])),
+            "eps": float(np.float32(10 ** rng.uniform(-3, -1)))}
+
+
+CASES = [draw(np.random.default_rng(1000 + k)) for k in range(24)]
+
+
+def sphere(n, seed):
+    pos, vel, mass = ics.plummer(n, seed=seed)
+    mass = mass * np.random.default_rng(seed).uniform(0.5, 1.5, n)
+    return (pos.astype(np.float32).astype(np.float64), vel.astype(np.float32).astype(np.float64),
+            mass.astype(np.float32).astype(np.float64))
+
+
+def t32(a):
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(a, dtype=np.float32).T)).to(DEV)
+
+
+@pytest.mark.parametrize("k", range(len(CASES)))
+def test_force(k):
+    c = CASES[k]
+    x, _, m = sphere(c["n"], 2000 + k)
+    shape = dict(ipl=c["ipl"], jtile=c["jtile"], nseg=c["nseg"])
+    acc, pot = api.force(t32(x), torch.from_numpy(m.astype(np.float32)).to(DEV), c["eps"],
+                         precision=c["precision"], **shape)
+    torch.cuda.synchronize()
+    ra, rp = oracle.force_all(x, m, c["eps"])
+    ea = rel_errors(acc.cpu().numpy().T, ra)
+    # The j == i potential term m_i / eps sits in an FP32 partial before its exact removal:
+    # each FP32 addition after it rounds a partial of at most m_i / eps + |phi_i| (all
+    # potential terms share a sign).  Those additions number fewer than one block,
+    # min(128, jtile), in the FP64 and compensated modes; plain FP32 adds the rest of the
+    # segment and the segment sum.
+    adds = min(128, c["jtile"]) if c["precision"] != "plain" else c["n"] + 1025
+    bound = 10 * TOL[c["precision"]] * np.abs(rp) + adds * U * (m / c["eps"] + np.abs(rp))
+    assert ea["rel_rms"] <= TOL[c["precision"]], (c, ea)
+    perr = np.abs(pot.cpu().numpy() - rp)
+    worst = int(np.argmax(perr / bound))
+    assert np.all(perr <= bound), (c, worst, float(perr[worst]), float(bound[worst]),
+                                   float(rp[worst]), float(m[worst]))
+
+
+@pytest.mark.parametrize("k", range(0, len(CASES), 2))
+def test_separate_sets(k):
+    c = CASES[k]
+    ni = max(1, c["n"] // 3)
+    xi, _, _ = sphere(ni, 3000 + k)
+    xj, _, mj = sphere(c["n"], 4000 + k)
+    xi = xi * 1.1 + 0.01
+    shape = dict(ipl=c["ipl"], jtile=c["jtile"], nseg=c["nseg"])
+    acc, pot = api.force_ij(t32(xi), t32(xj), torch.from_numpy(mj.astype(np.float32)).to(DEV),
+                            c["eps"], precision=c["precision"], **shape)
+    torch.cuda.synchronize()
+    ra, rp = oracle.force_ij(xj, mj, xi, c["eps"])
+    assert rel_errors(acc.cpu().numpy().T, ra)["rel_rms"] <= TOL[c["precision"]], c
+    assert rel_errors(pot.cpu().numpy(), rp)["rel_rms"] <= TOL[c["precision"]], c
+
+
+@pytest.mark.parametrize("k", range(1, len(CASES), 2))
+def test_force_jerk(k):
+    c = CASES[k]
+    x, v, m = sphere(c["n"], 5000 + k)
+    shape = dict(ipl=c["ipl"], jtile=c["jtile"], nseg=c["nseg"])
+    acc, jerk, _ = api.force_jerk(t32(x), t32(v), torch.from_numpy(m.astype(np.float32)).to(DEV),
+                                  c["eps"], precision=c["precision"], **shape)
+    torch.cuda.synchronize()
+    ra, rj, _ = oracle.force_jerk(x, v, m, c["eps"])
+    assert rel_errors(acc.cpu().numpy().T, ra)["rel_rms"] <= TOL[c["precision"]], c
+    # The jerk's per-particle error follows its condition number: bound it by the worst-case
+    # rounding of each pair term, 74 u B_ij with B_ij = m_j (|w| / s^3 + 3 |d.w| |d| / s^5),
+    # plus n u sum B for plain FP32 accumulation.
+    e2 = c["eps"] ** 2
+    scale = np.empty(c["n"])
+    for i in range(c["n"]):
+        d, w = x - x[i], v - v[i]
+        s2 = (d * d).sum(1) + e2
+        dn = np.sqrt((d * d).sum(1))
+        b = m * (np.sqrt((w * w).sum(1)) / s2 ** 1.5 + 3 * np.abs((d * w).sum(1)) * dn / s2 ** 2.5)
+        scale[i] = b.sum()
+    err = np.sqrt(((jerk.cpu().numpy().T - rj) ** 2).sum(1))
+    cmax = 74.0 + (c["n"] if c["precision"] == "plain" else 0)
+    assert np.all(err <= cmax * U * scale), (c, float((err / (U * scale)).max()))
