@@ -37,6 +37,10 @@ Accuracy: the CPU-baseline leg runs the FP64 oracle on a bounded sample of the s
 workload; its result gives the relative RMS and maximum (eq. (3)) errors of each
 mode, and its wall time the CPU rate.
 
+Warm-up: unless ``--warmup`` is given, each timed loop is preceded by enough untimed
+steps to keep the GPU busy for about a quarter of a second (``warmup`` in the line is
+the count of the headline mode), so the timed steps run at the steady rate.
+
 Prints one JSON line.  ``--gpus`` above 1 is refused: the path runs on one GPU.
 """
 from __future__ import annotations
@@ -131,7 +135,9 @@ def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=8)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed warm-up steps (default: enough to keep the GPU busy for "
+                         "about %.2f s, at least 2)" % WARM_SECONDS)
     ap.add_argument("--workload", default="plummer_131072",
                     choices=["plummer_131072", "plummer_2048", "stress_1m", "clusters_2048",
                              "adjoint_16384", "jerk_131072", "shard8_131072"])
@@ -156,8 +162,7 @@ class Timer:
 
     def run(self, call, reps, warmup=1):
         torch = self.torch
-        for _ in range(warmup):
-            call()
+        warm_up(torch, call, warmup)
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
               for _ in range(reps)]
         torch.cuda.synchronize()
@@ -169,6 +174,35 @@ class Timer:
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         return wall, [a.elapsed_time(b) for a, b in ev]
+
+
+WARM_SECONDS = 0.25
+WARMED = []
+
+
+def warm_up(torch, call, count):
+    """Untimed warm-up calls: ``count`` of them, or, for ``count=None``, as many as keep the
+    GPU busy for about WARM_SECONDS (at least two).  Launches shorter than a millisecond
+    reach their steady rate only after tens of milliseconds of continuous load (the 1/8
+    shard of N = 131072: 0.76 ms per evaluation for the first few, 0.65 ms after 50 ms).
+    Returns the number of calls made, also appended to WARMED."""
+    if count is not None:
+        for _ in range(count):
+            call()
+        torch.cuda.synchronize()
+        WARMED.append(count)
+        return count
+    call()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    call()
+    torch.cuda.synchronize()
+    more = max(0, int(np.ceil(WARM_SECONDS / max(time.perf_counter() - t0, 1e-6))) - 2)
+    for _ in range(more):
+        call()
+    torch.cuda.synchronize()
+    WARMED.append(more + 2)
+    return more + 2
 
 
 def one_thread(cpu, call, pairs, what):
@@ -227,9 +261,7 @@ def bench_plummer(args, torch, w):
         acc, _, _ = api.leapfrog(x, v, m, eps, dt, 0, precision=precision)
         pot = torch.empty(n, dtype=torch.float64, device=dev)
         g = api.LeapfrogGraph(x, v, m, eps, dt, 1, acc, pot=pot, precision=precision)
-        for _ in range(args.warmup):
-            g.launch()
-        torch.cuda.synchronize()
+        warm_up(torch, g.launch, args.warmup)
         x.copy_(x0)
         v.copy_(v0)
         api.leapfrog(x, v, m, eps, dt, 0, acc=acc, precision=precision)
@@ -385,9 +417,7 @@ def bench_clusters(args, torch, w):
         x, v = x0.clone(), v0.clone()
         acc, _ = plan.leapfrog(x, v, m, e, w.dt, 0)
         g = plan.graph(x, v, m, e, w.dt, 1, acc)
-        for _ in range(args.warmup):
-            g.launch()
-        torch.cuda.synchronize()
+        warm_up(torch, g.launch, args.warmup)
         wall, step_ms = timer.run(g.launch, args.steps, warmup=0)
         g.close()
         _, kms = timer.run(lambda: plan.force(p32, m, e), max(args.steps, 3))
@@ -622,9 +652,7 @@ def bench_jerk(args, torch, w):
         xs, vs = x.clone(), v.clone()
         ha, hj = api.hermite(xs, vs, m, eps, dt, 0, precision=precision)
         g = api.HermiteGraph(xs, vs, m, eps, dt, 1, ha, hj, precision=precision)
-        for _ in range(args.warmup):
-            g.launch()
-        torch.cuda.synchronize()
+        warm_up(torch, g.launch, args.warmup)
         xs.copy_(x)
         vs.copy_(v)
         api.hermite(xs, vs, m, eps, dt, 0, acc=ha, jerk=hj, precision=precision)
@@ -719,7 +747,7 @@ def main():
         "unit": "pair-interactions/s",
         "n_gpus": 1,
         "steps": args.steps,
-        "warmup": args.warmup,
+        "warmup": WARMED[0] if WARMED else args.warmup,
         "ms_per_step": body["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
