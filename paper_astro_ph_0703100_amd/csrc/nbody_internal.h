@@ -26,8 +26,11 @@ constexpr int kTPB = 256;
 // Largest number of j-segments a launch may split the j range into.
 constexpr int kMaxSeg = 1024;
 // Default number of j's summed in plain FP32 between two compensation / FP64 steps; a
-// pipeline may set its own (Op::kBlockJ), and the engine caps it at the j-tile.
-constexpr int kBlockJ = 32;
+// pipeline may set its own (Op::kBlockJ), and the engine caps it at the j-tile.  128
+// keeps the two-sums under 0.6 VALU operations per pair for every pipeline (force:
+// 4 outputs, jerk: 7, adjoint: 4).  The FP32 block sum adds at most 127 u sum |term|
+// (about sqrt(128) u sum |term| in practice), of the order of the pair rounding.
+constexpr int kBlockJ = 128;
 
 // Words (4-byte) of partial sums written per i-particle and j-segment.
 inline int partial_words(int precision) {

@@ -23,6 +23,7 @@ namespace {
 struct Adjoint {
     static constexpr int kJWords = 8;  // x, y, z, m, gx, gy, gz, p
     static constexpr int kOut = 4;     // dL/dx (3) and the positive sum of dL/dm
+    // 128 j's per compensation step (32 before: 1.8 % slower at N = 16384 and 131072).
     static constexpr int kBlockJ = nbody::kBlockJ;
     using Args = VjpArgs;
     struct IState {
