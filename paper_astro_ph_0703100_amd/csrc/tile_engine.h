@@ -41,6 +41,8 @@
 //   (FULL = false may skip the last output.)
 #pragma once
 
+#include <type_traits>
+
 #include "nbody_internal.h"
 
 namespace nbody {
@@ -254,65 +256,91 @@ __global__ __launch_bounds__(kTPB) void persistent_kernel(typename Op::Args a, B
     }
 }
 
-// Fixed-order sum of the segment partials of particle i (FP64 for FP64RED/COMP,
-// FP32 for PLAIN, returned widened), in r[0 .. NO).
+// Fixed-order sums of the segment partials.  Segment s holds, per output c, the words
+// [s][c][plane] (PLAIN: FP32; FP64RED: FP64) or [s][c][plane] = hi and [s][NO + c][plane]
+// = lo (COMP: FP32), summed as r += hi; r += lo.  The loads run a batch of segments
+// ahead of the additions, which stay strictly sequential in s: with few particles the
+// finalize has few waves and is bound by load latency, not bandwidth.
+template <int NO, int MODE>
+struct PartialLayout {
+    using T = typename std::conditional<MODE == NBODY_FP64RED, double, float>::type;
+    static constexpr int kWords = MODE == NBODY_COMP ? 2 : 1;  // hi (, lo) per output
+    static constexpr int kStride = kWords * NO;                 // words per segment and column
+};
+
+// One output c of particle i (FP64 for FP64RED/COMP, FP32 for PLAIN, returned widened).
+template <int NO, int MODE, int BATCH = 8>
+__device__ __forceinline__ double sum_partial_output(const void *part, int nseg, size_t plane,
+                                                     int i, int c) {
+    using L = PartialLayout<NO, MODE>;
+    using T = typename L::T;
+    const T *p = static_cast<const T *>(part) + i + (size_t)c * plane;
+    const size_t step = (size_t)L::kStride * plane;
+    const size_t lo = (size_t)NO * plane;  // COMP: offset of the lo word
+    using Acc = typename std::conditional<MODE == NBODY_PLAIN, float, double>::type;
+    Acc r = 0;
+    int s = 0;
+    for (; s + BATCH <= nseg; s += BATCH) {
+        T v[BATCH][L::kWords];
+#pragma unroll
+        for (int b = 0; b < BATCH; ++b) {
+            v[b][0] = p[(size_t)(s + b) * step];
+            if constexpr (L::kWords == 2) v[b][L::kWords - 1] = p[(size_t)(s + b) * step + lo];
+        }
+#pragma unroll
+        for (int b = 0; b < BATCH; ++b)
+#pragma unroll
+            for (int w = 0; w < L::kWords; ++w) r = r + (Acc)v[b][w];
+    }
+    for (; s < nseg; ++s) {
+        r = r + (Acc)p[(size_t)s * step];
+        if constexpr (L::kWords == 2) r = r + (Acc)p[(size_t)s * step + lo];
+    }
+    return (double)r;
+}
+
+// All NO outputs of particle i in r[0 .. NO), each with the rounding of the
+// corresponding sum_partial_output.
 template <int NO, int MODE>
 __device__ __forceinline__ void sum_partials(const void *part, int nseg, size_t plane, int i,
                                              double (&r)[NO]) {
-    if constexpr (MODE == NBODY_PLAIN) {
-        float f[NO];
+    using L = PartialLayout<NO, MODE>;
+    using T = typename L::T;
+    constexpr int BATCH = 4;
+    const T *p = static_cast<const T *>(part) + i;
+    const size_t step = (size_t)L::kStride * plane;
+    const size_t lo = (size_t)NO * plane;
+    using Acc = typename std::conditional<MODE == NBODY_PLAIN, float, double>::type;
+    Acc acc[NO];
 #pragma unroll
-        for (int c = 0; c < NO; ++c) f[c] = 0.0f;
-        const float *p = static_cast<const float *>(part) + i;
-        for (int s = 0; s < nseg; ++s)
+    for (int c = 0; c < NO; ++c) acc[c] = 0;
+    int s = 0;
+    for (; s + BATCH <= nseg; s += BATCH) {
+        T v[BATCH][NO][L::kWords];
 #pragma unroll
-            for (int c = 0; c < NO; ++c) f[c] = f[c] + p[((size_t)s * NO + c) * plane];
-#pragma unroll
-        for (int c = 0; c < NO; ++c) r[c] = (double)f[c];
-    } else if constexpr (MODE == NBODY_COMP) {
-        const float *p = static_cast<const float *>(part) + i;
-#pragma unroll
-        for (int c = 0; c < NO; ++c) r[c] = 0.0;
-        for (int s = 0; s < nseg; ++s)
+        for (int b = 0; b < BATCH; ++b)
 #pragma unroll
             for (int c = 0; c < NO; ++c) {
-                r[c] += (double)p[((size_t)s * 2 * NO + c) * plane];
-                r[c] += (double)p[((size_t)s * 2 * NO + NO + c) * plane];
+                v[b][c][0] = p[(size_t)(s + b) * step + (size_t)c * plane];
+                if constexpr (L::kWords == 2)
+                    v[b][c][L::kWords - 1] = p[(size_t)(s + b) * step + (size_t)c * plane + lo];
             }
-    } else {
-        const double *p = static_cast<const double *>(part) + i;
 #pragma unroll
-        for (int c = 0; c < NO; ++c) r[c] = 0.0;
-        for (int s = 0; s < nseg; ++s)
+        for (int b = 0; b < BATCH; ++b)
 #pragma unroll
-            for (int c = 0; c < NO; ++c) r[c] += p[((size_t)s * NO + c) * plane];
+            for (int c = 0; c < NO; ++c)
+#pragma unroll
+                for (int w = 0; w < L::kWords; ++w) acc[c] = acc[c] + (Acc)v[b][c][w];
     }
-}
-
-// The same fixed-order sum for one output c of particle i (identical rounding to the
-// corresponding element of sum_partials), so a finalize can spread outputs over threads.
-template <int NO, int MODE>
-__device__ __forceinline__ double sum_partial_output(const void *part, int nseg, size_t plane,
-                                                     int i, int c) {
-    if constexpr (MODE == NBODY_PLAIN) {
-        float f = 0.0f;
-        const float *p = static_cast<const float *>(part) + i;
-        for (int s = 0; s < nseg; ++s) f = f + p[((size_t)s * NO + c) * plane];
-        return (double)f;
-    } else if constexpr (MODE == NBODY_COMP) {
-        const float *p = static_cast<const float *>(part) + i;
-        double r = 0.0;
-        for (int s = 0; s < nseg; ++s) {
-            r += (double)p[((size_t)s * 2 * NO + c) * plane];
-            r += (double)p[((size_t)s * 2 * NO + NO + c) * plane];
+    for (; s < nseg; ++s)
+#pragma unroll
+        for (int c = 0; c < NO; ++c) {
+            acc[c] = acc[c] + (Acc)p[(size_t)s * step + (size_t)c * plane];
+            if constexpr (L::kWords == 2)
+                acc[c] = acc[c] + (Acc)p[(size_t)s * step + (size_t)c * plane + lo];
         }
-        return r;
-    } else {
-        const double *p = static_cast<const double *>(part) + i;
-        double r = 0.0;
-        for (int s = 0; s < nseg; ++s) r += p[((size_t)s * NO + c) * plane];
-        return r;
-    }
+#pragma unroll
+    for (int c = 0; c < NO; ++c) r[c] = (double)acc[c];
 }
 
 // Launch-shape dispatch over the template parameters.

@@ -141,29 +141,24 @@ struct AdjointTile {
     }
 };
 
+// One thread per (particle, output), as in the force finalize: fixed-order sums of the
+// segment partials, then dL/dx_k (outputs 0-2) or dL/dm_k with the j == k term removed
+// exactly (output 3).  Grid: (ceil(n / 256), 4 outputs, or 3 without dL/dm).
 template <int MODE>
 __global__ __launch_bounds__(256) void vjp_finalize_kernel(VjpFinalizeArgs a) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
     if (k >= a.n) return;
-    double r[4];
-    engine::sum_partials<4, MODE>(a.part, a.nseg, (size_t)a.npad, k, r);
-    const size_t n = (size_t)a.n;
-    if (a.accumulate) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) a.grad_pos[c * n + k] += r[c];
-    } else {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) a.grad_pos[c * n + k] = r[c];
+    const double r = engine::sum_partial_output<4, MODE>(a.part, a.nseg, (size_t)a.npad, k, c);
+    if (c < 3) {
+        double *g = a.grad_pos + (size_t)c * a.n + k;
+        *g = a.accumulate ? *g + r : r;
+        return;
     }
-    if (a.grad_mass) {
-        const float pk = a.gp ? (float)a.gp[k] : 0.0f;
-        const double self = (double)(pk * __builtin_amdgcn_rsqf(a.eps2));
-        const double gm = -(r[3] - self);
-        if (a.accumulate)
-            a.grad_mass[k] += gm;
-        else
-            a.grad_mass[k] = gm;
-    }
+    const float pk = a.gp ? (float)a.gp[k] : 0.0f;
+    const double self = (double)(pk * __builtin_amdgcn_rsqf(a.eps2));
+    const double gm = -(r - self);
+    a.grad_mass[k] = a.accumulate ? a.grad_mass[k] + gm : gm;
 }
 
 }  // namespace
@@ -190,7 +185,7 @@ nbody_status launch_vjp_tile(const TileCfg &cfg, int precision, const VjpTileArg
 
 nbody_status launch_vjp_finalize(int precision, const VjpFinalizeArgs &a, hipStream_t s) {
     if (a.n <= 0) return NBODY_OK;
-    const dim3 grid((a.n + 255) / 256);
+    const dim3 grid((a.n + 255) / 256, a.grad_mass ? 4 : 3);
     switch (precision) {
         case NBODY_PLAIN: hipLaunchKernelGGL(vjp_finalize_kernel<NBODY_PLAIN>, grid, dim3(256), 0, s, a); break;
         case NBODY_FP64RED: hipLaunchKernelGGL(vjp_finalize_kernel<NBODY_FP64RED>, grid, dim3(256), 0, s, a); break;
