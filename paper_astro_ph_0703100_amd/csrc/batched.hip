@@ -24,7 +24,7 @@ __global__ __launch_bounds__(256) void batched_finalize_kernel(BatchFinalizeArgs
     const int npad = a.npad[k];
     const void *base = static_cast<const float *>(a.part) + a.part_base[k];
     double r[4];
-    engine::sum_partials<4, MODE>(base, a.nseg[k], (size_t)npad, (int)col, r);
+    engine::sum_partials<4, MODE, 1>(base, a.nseg[k], (size_t)npad, (int)col, r);
     const float e = a.eps[k];
     const float self = a.m[p] * __builtin_amdgcn_rsqf(e * e);
     if constexpr (MODE == NBODY_PLAIN)

@@ -14,12 +14,12 @@ namespace {
 // block in the FP64 and compensated modes).
 // With kick_v set, the velocity kick of a leapfrog step follows in FP64.
 // Grid: (ceil(n / 256), 4 outputs, or 3 without potentials).
-template <int MODE>
+template <int MODE, int BATCH>
 __global__ __launch_bounds__(256) void finalize_kernel(FinalizeArgs a) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int c = blockIdx.y;
     if (i >= a.n) return;
-    double r = engine::sum_partial_output<4, MODE>(a.part, a.nseg, (size_t)a.npad, i, c);
+    double r = engine::sum_partial_output<4, MODE, BATCH>(a.part, a.nseg, (size_t)a.npad, i, c);
     if (c == 3) {
         if (a.exclude_self) {
             const float self = a.m[i] * __builtin_amdgcn_rsqf(a.eps2);
@@ -142,13 +142,23 @@ nbody_status launch_pair(const TileCfg &cfg, int precision, bool with_pot, const
     return NBODY_OK;
 }
 
+template <int MODE>
+void launch_finalize_mode(dim3 grid, bool deep, const FinalizeArgs &a, hipStream_t s) {
+    if (deep)
+        hipLaunchKernelGGL((finalize_kernel<MODE, 8>), grid, dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((finalize_kernel<MODE, 1>), grid, dim3(256), 0, s, a);
+}
+
 nbody_status launch_finalize(int precision, const FinalizeArgs &a, hipStream_t s) {
     if (a.n <= 0) return NBODY_OK;
-    const dim3 grid((a.n + 255) / 256, a.pot ? 4 : 3);
+    const int outputs = a.pot ? 4 : 3;
+    const dim3 grid((a.n + 255) / 256, outputs);
+    const bool deep = engine::finalize_batch(a.n, outputs) > 1;
     switch (precision) {
-        case NBODY_PLAIN: hipLaunchKernelGGL(finalize_kernel<NBODY_PLAIN>, grid, dim3(256), 0, s, a); break;
-        case NBODY_FP64RED: hipLaunchKernelGGL(finalize_kernel<NBODY_FP64RED>, grid, dim3(256), 0, s, a); break;
-        case NBODY_COMP: hipLaunchKernelGGL(finalize_kernel<NBODY_COMP>, grid, dim3(256), 0, s, a); break;
+        case NBODY_PLAIN: launch_finalize_mode<NBODY_PLAIN>(grid, deep, a, s); break;
+        case NBODY_FP64RED: launch_finalize_mode<NBODY_FP64RED>(grid, deep, a, s); break;
+        case NBODY_COMP: launch_finalize_mode<NBODY_COMP>(grid, deep, a, s); break;
         default: return set_error(NBODY_EINVAL, "unknown precision mode");
     }
     NBODY_HIP_CHECK(hipGetLastError());

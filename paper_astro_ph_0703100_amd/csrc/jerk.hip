@@ -130,12 +130,12 @@ struct GravityJerkTile {
 // One thread per (particle, output): fixed-order sums as in the force finalize, the
 // j == i potential term removed exactly.  Grid: (ceil(n / 256), 7 outputs, or 6
 // without potentials).
-template <int MODE>
+template <int MODE, int BATCH>
 __global__ __launch_bounds__(256) void jerk_finalize_kernel(JerkFinalizeArgs a) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int c = blockIdx.y;
     if (i >= a.n) return;
-    double r = engine::sum_partial_output<7, MODE>(a.part, a.nseg, (size_t)a.npad, i, c);
+    double r = engine::sum_partial_output<7, MODE, BATCH>(a.part, a.nseg, (size_t)a.npad, i, c);
     const size_t n = (size_t)a.n;
     if (c == 6) {
         if (a.exclude_self) {
@@ -175,13 +175,23 @@ nbody_status launch_jerk_tile(const TileCfg &cfg, int precision, bool with_pot,
     return NBODY_OK;
 }
 
+template <int MODE>
+void launch_jerk_finalize_mode(dim3 grid, bool deep, const JerkFinalizeArgs &a, hipStream_t s) {
+    if (deep)
+        hipLaunchKernelGGL((jerk_finalize_kernel<MODE, 8>), grid, dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((jerk_finalize_kernel<MODE, 1>), grid, dim3(256), 0, s, a);
+}
+
 nbody_status launch_jerk_finalize(int precision, const JerkFinalizeArgs &a, hipStream_t s) {
     if (a.n <= 0) return NBODY_OK;
-    const dim3 grid((a.n + 255) / 256, a.pot ? 7 : 6);
+    const int outputs = a.pot ? 7 : 6;
+    const dim3 grid((a.n + 255) / 256, outputs);
+    const bool deep = engine::finalize_batch(a.n, outputs) > 1;
     switch (precision) {
-        case NBODY_PLAIN: hipLaunchKernelGGL(jerk_finalize_kernel<NBODY_PLAIN>, grid, dim3(256), 0, s, a); break;
-        case NBODY_FP64RED: hipLaunchKernelGGL(jerk_finalize_kernel<NBODY_FP64RED>, grid, dim3(256), 0, s, a); break;
-        case NBODY_COMP: hipLaunchKernelGGL(jerk_finalize_kernel<NBODY_COMP>, grid, dim3(256), 0, s, a); break;
+        case NBODY_PLAIN: launch_jerk_finalize_mode<NBODY_PLAIN>(grid, deep, a, s); break;
+        case NBODY_FP64RED: launch_jerk_finalize_mode<NBODY_FP64RED>(grid, deep, a, s); break;
+        case NBODY_COMP: launch_jerk_finalize_mode<NBODY_COMP>(grid, deep, a, s); break;
         default: return set_error(NBODY_EINVAL, "unknown precision mode");
     }
     NBODY_HIP_CHECK(hipGetLastError());

@@ -268,8 +268,16 @@ struct PartialLayout {
     static constexpr int kStride = kWords * NO;                 // words per segment and column
 };
 
+// Segments whose loads a finalize thread issues ahead of its additions: 8 when the
+// finalize has under 4 waves per SIMD (bound by load latency: at N = 16384 the force
+// finalize went from 18 to 6 us), 1 otherwise (bound by bandwidth; a deeper batch only
+// scatters the DRAM accesses: at N = 131072 it went from 26 to 39 us).
+inline int finalize_batch(int64_t n, int outputs) {
+    return n * outputs < (int64_t)4 * 1024 * 64 ? 8 : 1;
+}
+
 // One output c of particle i (FP64 for FP64RED/COMP, FP32 for PLAIN, returned widened).
-template <int NO, int MODE, int BATCH = 8>
+template <int NO, int MODE, int BATCH>
 __device__ __forceinline__ double sum_partial_output(const void *part, int nseg, size_t plane,
                                                      int i, int c) {
     using L = PartialLayout<NO, MODE>;
@@ -301,12 +309,11 @@ __device__ __forceinline__ double sum_partial_output(const void *part, int nseg,
 
 // All NO outputs of particle i in r[0 .. NO), each with the rounding of the
 // corresponding sum_partial_output.
-template <int NO, int MODE>
+template <int NO, int MODE, int BATCH>
 __device__ __forceinline__ void sum_partials(const void *part, int nseg, size_t plane, int i,
                                              double (&r)[NO]) {
     using L = PartialLayout<NO, MODE>;
     using T = typename L::T;
-    constexpr int BATCH = 4;
     const T *p = static_cast<const T *>(part) + i;
     const size_t step = (size_t)L::kStride * plane;
     const size_t lo = (size_t)NO * plane;

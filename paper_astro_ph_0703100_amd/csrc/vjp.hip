@@ -144,12 +144,12 @@ struct AdjointTile {
 // One thread per (particle, output), as in the force finalize: fixed-order sums of the
 // segment partials, then dL/dx_k (outputs 0-2) or dL/dm_k with the j == k term removed
 // exactly (output 3).  Grid: (ceil(n / 256), 4 outputs, or 3 without dL/dm).
-template <int MODE>
+template <int MODE, int BATCH>
 __global__ __launch_bounds__(256) void vjp_finalize_kernel(VjpFinalizeArgs a) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     const int c = blockIdx.y;
     if (k >= a.n) return;
-    const double r = engine::sum_partial_output<4, MODE>(a.part, a.nseg, (size_t)a.npad, k, c);
+    const double r = engine::sum_partial_output<4, MODE, BATCH>(a.part, a.nseg, (size_t)a.npad, k, c);
     if (c < 3) {
         double *g = a.grad_pos + (size_t)c * a.n + k;
         *g = a.accumulate ? *g + r : r;
@@ -183,13 +183,23 @@ nbody_status launch_vjp_tile(const TileCfg &cfg, int precision, const VjpTileArg
     return NBODY_OK;
 }
 
+template <int MODE>
+void launch_vjp_finalize_mode(dim3 grid, bool deep, const VjpFinalizeArgs &a, hipStream_t s) {
+    if (deep)
+        hipLaunchKernelGGL((vjp_finalize_kernel<MODE, 8>), grid, dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((vjp_finalize_kernel<MODE, 1>), grid, dim3(256), 0, s, a);
+}
+
 nbody_status launch_vjp_finalize(int precision, const VjpFinalizeArgs &a, hipStream_t s) {
     if (a.n <= 0) return NBODY_OK;
-    const dim3 grid((a.n + 255) / 256, a.grad_mass ? 4 : 3);
+    const int outputs = a.grad_mass ? 4 : 3;
+    const dim3 grid((a.n + 255) / 256, outputs);
+    const bool deep = engine::finalize_batch(a.n, outputs) > 1;
     switch (precision) {
-        case NBODY_PLAIN: hipLaunchKernelGGL(vjp_finalize_kernel<NBODY_PLAIN>, grid, dim3(256), 0, s, a); break;
-        case NBODY_FP64RED: hipLaunchKernelGGL(vjp_finalize_kernel<NBODY_FP64RED>, grid, dim3(256), 0, s, a); break;
-        case NBODY_COMP: hipLaunchKernelGGL(vjp_finalize_kernel<NBODY_COMP>, grid, dim3(256), 0, s, a); break;
+        case NBODY_PLAIN: launch_vjp_finalize_mode<NBODY_PLAIN>(grid, deep, a, s); break;
+        case NBODY_FP64RED: launch_vjp_finalize_mode<NBODY_FP64RED>(grid, deep, a, s); break;
+        case NBODY_COMP: launch_vjp_finalize_mode<NBODY_COMP>(grid, deep, a, s); break;
         default: return set_error(NBODY_EINVAL, "unknown precision mode");
     }
     NBODY_HIP_CHECK(hipGetLastError());
