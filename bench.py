@@ -363,7 +363,7 @@ def bench_stress(args, torch, w):
     cpu, errors = None, {}
     if not args.no_cpu_baseline:
         import oracle
-        k = args.cpu_sample if args.cpu_sample > 0 else 2048
+        k = args.cpu_sample if args.cpu_sample > 0 else 8192
         idx = ics.stratified_indices(core, k, seed=w.seed + 1000)
         t0 = time.perf_counter()
         ra, rp = oracle.force_sampled(pos, m32.astype(np.float64), eps, idx)
@@ -591,16 +591,16 @@ def bench_shard(args, torch, w):
     cpu, errors = None, {}
     if not args.no_cpu_baseline:
         import oracle
-        k = 2048 if args.cpu_sample <= 0 else min(ni, args.cpu_sample)
-        idx = ics.sample_indices(ni, k, seed=w.seed + 1000)
+        k = ni if args.cpu_sample <= 0 else min(ni, args.cpu_sample)
+        idx = np.arange(ni) if k == ni else ics.sample_indices(ni, k, seed=w.seed + 1000)
         x64 = p32.T.astype(np.float64)
         t0 = time.perf_counter()
         ra, rp = oracle.force_ij(x64, m32.astype(np.float64), x64[idx], eps)
         ct = time.perf_counter() - t0
         cpu = {"value": k * float(n) / ct, "unit": "pair-interactions/s",
                "cores": oracle.threads(), "kind": "oracle",
-               "sample": "force+potential of %d sampled i-particles of the shard from all %d, "
-                         "FP64 (%.1f s)" % (k, n, ct)}
+               "sample": "force+potential of %s i-particles of the shard from all %d, "
+                         "FP64 (%.1f s)" % ("all %d" % k if k == ni else "%d sampled" % k, n, ct)}
         i1 = idx[::8]
         one_thread(cpu, lambda: oracle.force_ij(x64, m32.astype(np.float64), x64[i1], eps),
                    float(i1.size) * n, "%d of those i-particles" % i1.size)
@@ -672,7 +672,7 @@ def bench_jerk(args, torch, w):
     cpu, errors = None, {}
     if not args.no_cpu_baseline:
         import oracle
-        k = 8192 if args.cpu_sample <= 0 else min(n, args.cpu_sample)
+        k = 32768 if args.cpu_sample <= 0 else min(n, args.cpu_sample)
         idx = ics.sample_indices(n, k, seed=w.seed + 1000)
         t0 = time.perf_counter()
         ra, rj, rp = oracle.force_jerk(pos, vel, m32.astype(np.float64), eps, idx=idx)
