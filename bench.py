@@ -160,7 +160,7 @@ class Timer:
         self.torch = torch
         self.stream = torch.cuda.current_stream()
 
-    def run(self, call, reps, warmup=1):
+    def run(self, call, reps, warmup=None):
         torch = self.torch
         warm_up(torch, call, warmup)
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -272,7 +272,7 @@ def bench_plummer(args, torch, w):
         opts = api.make_opts(precision=precision)
         _, kms = timer.run(lambda: _lib.nbody_force_ex(n, p32.data_ptr(), m.data_ptr(), eps,
                                                        fa.data_ptr(), fp.data_ptr(), opts, sp),
-                           max(args.steps, 3))
+                           max(args.steps, 3), warmup=args.warmup)
         a64, p64 = api.force_f64(x0, m, eps, precision=precision)
         torch.cuda.synchronize()
         res[precision] = {"wall": wall, "step_ms": step_ms, "kernel_ms": float(np.mean(kms)),
@@ -420,7 +420,7 @@ def bench_clusters(args, torch, w):
         warm_up(torch, g.launch, args.warmup)
         wall, step_ms = timer.run(g.launch, args.steps, warmup=0)
         g.close()
-        _, kms = timer.run(lambda: plan.force(p32, m, e), max(args.steps, 3))
+        _, kms = timer.run(lambda: plan.force(p32, m, e), max(args.steps, 3), warmup=args.warmup)
         a, _ = plan.force_f64(x0, m, e)
         torch.cuda.synchronize()
         res[precision] = {"wall": wall, "step_ms": step_ms, "kernel_ms": float(np.mean(kms)),
@@ -507,7 +507,7 @@ def bench_adjoint(args, torch, w):
     sp = torch.cuda.current_stream().cuda_stream
     _, kms = timer.run(lambda: _lib.nbody_force_vjp(n, p32.data_ptr(), m32.data_ptr(), eps,
                                                     g.data_ptr(), None, gx.data_ptr(),
-                                                    gm.data_ptr(), opts, sp), 8)
+                                                    gm.data_ptr(), opts, sp), 8, warmup=args.warmup)
     # The same kernel on the N = 131072 sphere, where the grid holds many rounds of blocks.
     nb = 131072
     xb, _, mb = ics.plummer(nb, seed=2, velocities=False)
@@ -519,7 +519,7 @@ def bench_adjoint(args, torch, w):
     eb = float(np.float32(ics.plummer_131072_eps(nb)))
     _, kmb = timer.run(lambda: _lib.nbody_force_vjp(nb, pb.data_ptr(), mbt.data_ptr(), eb,
                                                     gb.data_ptr(), None, gxb.data_ptr(),
-                                                    gmb.data_ptr(), opts, sp), 3)
+                                                    gmb.data_ptr(), opts, sp), 3, warmup=args.warmup)
     big = roofline("adjoint", float(nb) * nb, float(np.mean(kmb)), "tile_kernel<Adjoint>")
     pairs_step = float(n) * n * 2 * (w.steps + 1)
     print("bench: rollout+gradient %.3f ms/step, adjoint kernel %.3f ms (N=%d: %.3f ms)" %
@@ -664,7 +664,7 @@ def bench_jerk(args, torch, w):
         _, kms = timer.run(lambda: _lib.nbody_force_jerk(n, p32.data_ptr(), v32.data_ptr(),
                                                          m.data_ptr(), eps, acc.data_ptr(),
                                                          jerk.data_ptr(), pot.data_ptr(), opts, sp),
-                           max(args.steps, 3))
+                           max(args.steps, 3), warmup=args.warmup)
         res[precision] = {"wall": wall, "kernel_ms": float(np.mean(kms)), "out": host}
         print("bench: %-8s %d Hermite steps  %.3f ms/step (wall)  jerk kernel %.3f ms"
               % (precision, args.steps, wall / args.steps * 1e3, np.mean(kms)),
