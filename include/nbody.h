@@ -176,6 +176,32 @@ NBODY_API nbody_status nbody_force_jerk_f64(int64_t n, const double *pos64, cons
                                             const float *mass, float eps, double *acc,
                                             double *jerk, double *pot, const nbody_opts *opts,
                                             void *stream);
+
+/* ------------------------------------------------------------------------------
+ * Force, jerk and potential on one set of particles from another: the force-jerk-
+ * potential pipeline (Appendix A) behind the paper's separate i- and j-set library
+ * call (Sec. 3.1).  A Hermite code with individual time steps evaluates only its
+ * active particles this way, against the predicted state of all of them.  Every
+ * (i, j) pair is summed with the formulas of nbody_force_jerk and one softening for
+ * all: no pair is a self pair, so an i-particle that coincides with a j-particle gets
+ * zero acceleration and jerk and -m_j/eps potential from it (NaN if eps = 0).
+ *   ni      i-particles, 0 <= ni < 2^30; pos_i, vel_i float [3][ni] (read)
+ *   nj      j-particles, 0 <= nj < 2^30; pos_j, vel_j float [3][nj], mass_j float [nj]
+ *           (read)
+ *   eps     softening (finite, >= 0; eps^2 zero or a normal float).  Coordinates must
+ *           stay well below 1e18 in magnitude (unused slots of a j-tile sit there).
+ *   acc     double [3][ni], jerk double [3][ni] (written); pot double [ni] or NULL
+ *   opts    precision, ipl, jtile, nseg and workspace apply; centre and self_pot are
+ *           ignored; NULL = defaults
+ * nj = 0 writes zeros.  Outputs must not alias inputs.  Scratch:
+ * nbody_workspace_size_jerk_ij bytes (the per-device cache when opts->workspace is NULL).
+ * ---------------------------------------------------------------------------- */
+NBODY_API nbody_status nbody_force_jerk_ij(int64_t ni, const float *pos_i, const float *vel_i,
+                                           int64_t nj, const float *pos_j, const float *vel_j,
+                                           const float *mass_j, float eps, double *acc,
+                                           double *jerk, double *pot, const nbody_opts *opts,
+                                           void *stream);
+NBODY_API size_t nbody_workspace_size_jerk_ij(int64_t ni, int64_t nj, const nbody_opts *opts);
 NBODY_API size_t nbody_workspace_size_jerk(int64_t n, const nbody_opts *opts);
 
 /* Morton (Z-order) permutation of FP64 positions pos64 double [3][n]: perm int32 [n]

@@ -16,6 +16,9 @@ Parity status of each function (what pins it; the pins are in tests/test_oracle.
   force_jerk          : two-body closed form, central time differences of
       force_all along x + v t, 50-digit brute force, sum_i m_i jerk_i = 0,
       exact power-of-two scaling of v, Galilean invariance.
+  force_jerk_ij       : central time differences of the (pinned) force_ij along
+      straight-line motion of both sets; on i-set = j-set it equals force_jerk
+      exactly in a and the jerk, and in phi up to the self term -m_i/eps.
   vjp                 : central finite differences of force_all, translation
       invariance, degree-1 homogeneity in the masses.
   rollout             : time reversibility, second-order energy error, two-body
@@ -181,6 +184,22 @@ def force_jerk(x, v, m, eps, idx=None):
     k = idx.size
     acc, jerk, pot = np.empty((k, 3)), np.empty((k, 3)), np.empty(k)
     _load().oracle_force_jerk(n, _p(x), _p(v), _p(m), k, _p(xi), _p(vi), _p(idx, _L), float(eps),
+                              _p(acc), _p(jerk), _p(pot))
+    return acc, jerk, pot
+
+
+def force_jerk_ij(xj, vj, mj, xi, vi, eps):
+    """(acc, jerk, pot) on the i-set ``xi``, ``vi`` ``(ni, 3)`` from the j-set; every
+    (i, j) pair is summed (no self pair), one softening ``eps`` for all."""
+    xj = _f64(xj)
+    nj = xj.shape[0]
+    vj = _f64(vj, (nj, 3))
+    mj = _f64(mj, (nj,))
+    xi = _f64(xi)
+    ni = xi.shape[0]
+    vi = _f64(vi, (ni, 3))
+    acc, jerk, pot = np.empty((ni, 3)), np.empty((ni, 3)), np.empty(ni)
+    _load().oracle_force_jerk(nj, _p(xj), _p(vj), _p(mj), ni, _p(xi), _p(vi), None, float(eps),
                               _p(acc), _p(jerk), _p(pot))
     return acc, jerk, pot
 

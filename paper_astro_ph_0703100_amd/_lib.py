@@ -75,6 +75,8 @@ SIGNATURES = {
     "nbody_force_ij": (_I32, [_I64, _P, _P, _I64, _P, _P, _F, _P, _P, _OPTS, _P]),
     "nbody_workspace_size_ij": (ctypes.c_size_t, [_I64, _I64, _OPTS]),
     "nbody_force_jerk": (_I32, [_I64, _P, _P, _P, _F, _P, _P, _P, _OPTS, _P]),
+    "nbody_force_jerk_ij": (_I32, [_I64, _P, _P, _I64, _P, _P, _P, _F, _P, _P, _P, _OPTS, _P]),
+    "nbody_workspace_size_jerk_ij": (ctypes.c_size_t, [_I64, _I64, _OPTS]),
     "nbody_force_jerk_f64": (_I32, [_I64, _P, _P, _P, _F, _P, _P, _P, _OPTS, _P]),
     "nbody_workspace_size_jerk": (ctypes.c_size_t, [_I64, _OPTS]),
     "nbody_hermite": (_I32, [_I64, _P, _P, _P, _F, _D, _I32, _P, _P, _I32, _OPTS, _P]),
@@ -200,6 +202,17 @@ def nbody_force_jerk_f64(n, pos64, vel64, mass, eps, acc, jerk, pot, opts, strea
     st = load().nbody_force_jerk_f64(n, pos64, vel64, mass, eps, acc, jerk, pot, _opt_ref(opts),
                                      stream)
     return _check(st, "nbody_force_jerk_f64") if check else st
+
+
+def nbody_force_jerk_ij(ni, pos_i, vel_i, nj, pos_j, vel_j, mass_j, eps, acc, jerk, pot, opts,
+                        stream, check=True):
+    st = load().nbody_force_jerk_ij(ni, pos_i, vel_i, nj, pos_j, vel_j, mass_j, eps, acc, jerk,
+                                    pot, _opt_ref(opts), stream)
+    return _check(st, "nbody_force_jerk_ij") if check else st
+
+
+def nbody_workspace_size_jerk_ij(ni: int, nj: int, opts: nbody_opts | None) -> int:
+    return int(load().nbody_workspace_size_jerk_ij(ni, nj, _opt_ref(opts)))
 
 
 def nbody_workspace_size_jerk(n: int, opts: nbody_opts | None) -> int:

@@ -128,6 +128,31 @@ def force_jerk(pos: torch.Tensor, vel: torch.Tensor, mass: torch.Tensor, eps: fl
     return acc, jerk, pot
 
 
+def force_jerk_ij(pos_i: torch.Tensor, vel_i: torch.Tensor, pos_j: torch.Tensor,
+                  vel_j: torch.Tensor, mass_j: torch.Tensor, eps: float = 0.0,
+                  precision: str = "comp", with_pot: bool = True, out=None, **kw):
+    """``(acc, jerk, pot)`` (float64, ``[3, ni]``, ``[3, ni]``, ``[ni]``) on the i-set from
+    the j-set, float32 ``[3, n]`` inputs; every pair counts (no self pair)."""
+    ni = _check_pos(pos_i, torch.float32, "pos_i")
+    if _check_pos(vel_i, torch.float32, "vel_i") != ni:
+        raise ValueError("vel_i must have the shape of pos_i")
+    nj = _check_pos(pos_j, torch.float32, "pos_j")
+    if _check_pos(vel_j, torch.float32, "vel_j") != nj:
+        raise ValueError("vel_j must have the shape of pos_j")
+    _check_vec(mass_j, nj, torch.float32, "mass_j")
+    dev = pos_i.device
+    acc, jerk, pot = out if out is not None else (
+        torch.empty((3, ni), dtype=torch.float64, device=dev),
+        torch.empty((3, ni), dtype=torch.float64, device=dev),
+        torch.empty(ni, dtype=torch.float64, device=dev) if with_pot else None)
+    opts = make_opts(precision=precision, **kw)
+    _lib.nbody_force_jerk_ij(ni, pos_i.data_ptr(), vel_i.data_ptr(), nj, pos_j.data_ptr(),
+                             vel_j.data_ptr(), mass_j.data_ptr(), float(eps), acc.data_ptr(),
+                             jerk.data_ptr(), pot.data_ptr() if pot is not None else None, opts,
+                             stream_ptr())
+    return acc, jerk, pot
+
+
 def morton_order(pos64: torch.Tensor) -> torch.Tensor:
     """int32 permutation ``[n]`` ordering the particles along the Z-curve."""
     n = _check_pos(pos64, torch.float64, "pos64")

@@ -205,6 +205,54 @@ nbody_status nbody_force_jerk_f64(int64_t n, const double *pos64, const double *
                          jerk_f64_layout(ws, n, cfg, o.precision), s);
 }
 
+nbody_status nbody_force_jerk_ij(int64_t ni, const float *pos_i, const float *vel_i, int64_t nj,
+                                 const float *pos_j, const float *vel_j, const float *mass_j,
+                                 float eps, double *acc, double *jerk, double *pot,
+                                 const nbody_opts *opts, void *stream) {
+    clear_error();
+    nbody_opts o = resolve_opts(opts);
+    if (ni < 0 || ni > INT32_MAX / 2 || nj < 0 || nj > INT32_MAX / 2)
+        return set_error(NBODY_EINVAL, "ni and nj must be in [0, 2^30)");
+    if (ni > 0 && (!pos_i || !vel_i || !acc || !jerk))
+        return set_error(NBODY_EINVAL, "pos_i, vel_i, acc and jerk must not be NULL");
+    if (ni > 0 && nj > 0 && (!pos_j || !vel_j || !mass_j))
+        return set_error(NBODY_EINVAL, "pos_j, vel_j and mass_j must not be NULL");
+    const float e2 = eps * eps;
+    if (!std::isfinite(eps) || !(eps >= 0.0f) || !std::isfinite(e2) || (eps > 0.0f && !(e2 >= FLT_MIN)))
+        return set_error(NBODY_EINVAL, "eps must be finite and >= 0 with eps^2 zero or a normal float");
+    if (o.precision < NBODY_PLAIN || o.precision > NBODY_COMP)
+        return set_error(NBODY_EINVAL, "precision must be NBODY_PLAIN, NBODY_FP64RED or NBODY_COMP");
+    if (misaligned(pos_i) || misaligned(vel_i) || misaligned(pos_j) || misaligned(vel_j) ||
+        misaligned(mass_j) || misaligned(acc) || misaligned(jerk) || misaligned(pot))
+        return set_error(NBODY_EINVAL, "misaligned array argument");
+    if (ni == 0) return NBODY_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    nbody_status st;
+    if (nj == 0) {
+        if ((st = launch_fill_f64(3 * ni, acc, 0.0, s))) return st;
+        if ((st = launch_fill_f64(3 * ni, jerk, 0.0, s))) return st;
+        return pot ? launch_fill_f64(ni, pot, 0.0, s) : NBODY_OK;
+    }
+    TileCfg cfg;
+    if ((st = choose_cfg_ij(KERNEL_JERK, ni, nj, o.precision, o, &cfg))) return st;
+    void *ws = nullptr;
+    if ((st = get_workspace(o, jerk_partial_bytes(cfg, o.precision), s, &ws))) return st;
+    JerkIJArgs a{pos_i, pos_i + ni, pos_i + 2 * ni, vel_i, vel_i + ni, vel_i + 2 * ni,
+                 pos_j, pos_j + nj, pos_j + 2 * nj, mass_j, vel_j, vel_j + nj, vel_j + 2 * nj,
+                 (int)ni, (int)nj, cfg.seg_len, e2, ws, cfg.npad};
+    if ((st = launch_jerk_ij(cfg, o.precision, pot != nullptr, a, s))) return st;
+    JerkFinalizeArgs fa{ws, cfg.nseg, cfg.npad, (int)ni, nullptr, e2, 0, acc, jerk, pot};
+    return launch_jerk_finalize(o.precision, fa, s);
+}
+
+size_t nbody_workspace_size_jerk_ij(int64_t ni, int64_t nj, const nbody_opts *opts) {
+    nbody_opts o = resolve_opts(opts);
+    if (ni <= 0 || nj <= 0) return 0;
+    TileCfg c;
+    if (choose_cfg_ij(KERNEL_JERK, ni, nj, o.precision, o, &c) != NBODY_OK) return 0;
+    return jerk_partial_bytes(c, o.precision);
+}
+
 size_t nbody_workspace_size_hermite(int64_t n, const nbody_opts *opts) {
     nbody_opts o = resolve_opts(opts);
     if (n <= 0) return 0;

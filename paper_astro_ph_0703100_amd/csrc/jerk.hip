@@ -6,8 +6,8 @@
 //   phi_i  -=  m_j / s
 // j-records are 8 floats (x, y, z, m, vx, vy, vz, 0: two LDS reads per j); i-records
 // hold position and velocity.  27 FP32 VALU operations and one v_rsq_f32 per pair.
-// Two pipelines: FP32 inputs (GravityJerk) and FP64 state relative to per-i-tile
-// centres (GravityJerkTile).
+// Three pipelines: FP32 inputs (GravityJerk), FP64 state relative to per-i-tile centres
+// (GravityJerkTile), and separate i- and j-sets (GravityJerkIJ).
 #include "tile_engine.h"
 
 namespace nbody {
@@ -127,6 +127,45 @@ struct GravityJerkTile {
     }
 };
 
+// Separate i- and j-sets (an active subset of a system against all of it, or two
+// systems): every (i, j) pair is summed, with one softening for all.  Padding
+// j-records are massless and far away (1e18), so their terms are exactly zero even
+// with eps = 0 (s^2 stays a finite normal float and every product with m = 0 is 0).
+struct GravityJerkIJ {
+    static constexpr int kJWords = 8;
+    static constexpr int kOut = 7;
+    static constexpr int kBlockJ = GravityJerk::kBlockJ;
+    using Args = JerkIJArgs;
+    using IState = GravityJerk::IState;
+    struct Ctx {};
+    static __device__ __forceinline__ int n_i(const Args &a) { return a.ni; }
+    static __device__ __forceinline__ int n_j(const Args &a) { return a.nj; }
+    static __device__ __forceinline__ Ctx make_ctx(const Args &, int) { return {}; }
+    static __device__ __forceinline__ IState load_i(const Args &a, const Ctx &, int i) {
+        return {a.xi[i], a.yi[i], a.zi[i], a.vxi[i], a.vyi[i], a.vzi[i]};
+    }
+    static __device__ __forceinline__ void load_j(const Args &a, const Ctx &, int j, float (&r)[8]) {
+        r[0] = a.x[j];
+        r[1] = a.y[j];
+        r[2] = a.z[j];
+        r[3] = a.m[j];
+        r[4] = a.vx[j];
+        r[5] = a.vy[j];
+        r[6] = a.vz[j];
+        r[7] = 0.0f;
+    }
+    static __device__ __forceinline__ void pad_j(float (&r)[8]) {
+        r[0] = r[1] = r[2] = 1e18f;
+#pragma unroll
+        for (int c = 3; c < 8; ++c) r[c] = 0.0f;
+    }
+    template <bool POT>
+    static __device__ __forceinline__ void pair(const float *j, const IState &i, float eps2,
+                                                float (&acc)[7]) {
+        jerk_pair<POT>(j, i.x, i.y, i.z, i.vx, i.vy, i.vz, eps2, acc);
+    }
+};
+
 // One thread per (particle, output): fixed-order sums as in the force finalize, the
 // j == i potential term removed exactly.  Grid: (ceil(n / 256), 7 outputs, or 6
 // without potentials).
@@ -181,6 +220,16 @@ void launch_jerk_finalize_mode(dim3 grid, bool deep, const JerkFinalizeArgs &a, 
         hipLaunchKernelGGL((jerk_finalize_kernel<MODE, 8>), grid, dim3(256), 0, s, a);
     else
         hipLaunchKernelGGL((jerk_finalize_kernel<MODE, 1>), grid, dim3(256), 0, s, a);
+}
+
+nbody_status launch_jerk_ij(const TileCfg &cfg, int precision, bool with_pot, const JerkIJArgs &a,
+                            hipStream_t s) {
+    auto fn = engine::pick_tile<GravityJerkIJ>(cfg.ipl, cfg.jt, precision, with_pot);
+    if (!fn) return set_error(NBODY_EUNSUPPORTED, "no separate-set jerk kernel for this shape");
+    if (cfg.itiles <= 0 || cfg.nseg <= 0) return NBODY_OK;
+    hipLaunchKernelGGL(fn, dim3(cfg.itiles, cfg.nseg), dim3(kTPB), 0, s, a);
+    NBODY_HIP_CHECK(hipGetLastError());
+    return NBODY_OK;
 }
 
 nbody_status launch_jerk_finalize(int precision, const JerkFinalizeArgs &a, hipStream_t s) {

@@ -109,6 +109,19 @@ struct JerkTileArgs {
     int itile;                   // particles per i-tile (256 * IPL)
 };
 
+// Force-jerk-potential with separate i- and j-sets (FP32 inputs, uniform softening).
+struct JerkIJArgs {
+    const float *xi, *yi, *zi;     // i positions [3][ni]
+    const float *vxi, *vyi, *vzi;  // i velocities [3][ni]
+    const float *x, *y, *z, *m;    // j positions [3][nj] and masses [nj]
+    const float *vx, *vy, *vz;     // j velocities [3][nj]
+    int ni, nj;
+    int seg_len;
+    float eps2;
+    void *part;
+    int npad;
+};
+
 struct JerkFinalizeArgs {
     const void *part;
     int nseg, npad, n;
@@ -318,6 +331,8 @@ nbody_status launch_jerk(const TileCfg &cfg, int precision, bool with_pot, const
 nbody_status launch_jerk_finalize(int precision, const JerkFinalizeArgs &a, hipStream_t s);
 nbody_status launch_jerk_tile(const TileCfg &cfg, int precision, bool with_pot,
                               const JerkTileArgs &a, hipStream_t s);
+nbody_status launch_jerk_ij(const TileCfg &cfg, int precision, bool with_pot, const JerkIJArgs &a,
+                            hipStream_t s);
 // Fourth-order Hermite predictor and corrector (hermite.hip).
 nbody_status launch_hermite_predict(int64_t n, const double *x, const double *v, const double *a,
                                     const double *j, double dt, double *xp, double *vp,

@@ -105,6 +105,36 @@ def test_force_jerk_rejects_invalid_arguments(entry, args, what):
     assert st == _lib.NBODY_EINVAL, what
 
 
+# nbody_force_jerk_ij(ni, pos_i, vel_i, nj, pos_j, vel_j, mass_j, eps, acc, jerk, pot, ...)
+@pytest.mark.parametrize("args,what", [
+    ((-1, FAKE, FAKE, 10, FAKE, FAKE, FAKE, 0.1, FAKE, FAKE, None), "negative ni"),
+    ((10, FAKE, FAKE, 1 << 31, FAKE, FAKE, FAKE, 0.1, FAKE, FAKE, None), "nj too large"),
+    ((10, FAKE, None, 10, FAKE, FAKE, FAKE, 0.1, FAKE, FAKE, None), "NULL vel_i"),
+    ((10, FAKE, FAKE, 10, FAKE, None, FAKE, 0.1, FAKE, FAKE, None), "NULL vel_j"),
+    ((10, FAKE, FAKE, 10, FAKE, FAKE, None, 0.1, FAKE, FAKE, None), "NULL mass_j"),
+    ((10, FAKE, FAKE, 10, FAKE, FAKE, FAKE, 0.1, FAKE, None, None), "NULL jerk"),
+    ((10, FAKE, FAKE, 10, FAKE, FAKE, FAKE, -1.0, FAKE, FAKE, None), "eps < 0"),
+    ((10, FAKE, FAKE, 10, FAKE, FAKE, FAKE, float("inf"), FAKE, FAKE, None), "eps inf"),
+    ((10, FAKE, FAKE + 2, 10, FAKE, FAKE, FAKE, 0.1, FAKE, FAKE, None), "misaligned vel_i"),
+    ((10, FAKE, FAKE, 10, FAKE, FAKE, FAKE, 0.1, FAKE, FAKE, FAKE + 4), "misaligned pot"),
+])
+def test_force_jerk_ij_rejects_invalid_arguments(args, what):
+    st = _lib.nbody_force_jerk_ij(*args, None, None, check=False)
+    assert st == _lib.NBODY_EINVAL, what
+    assert _lib.nbody_last_error() != ""
+
+
+def test_force_jerk_ij_empty_i_set_and_options():
+    assert _lib.nbody_force_jerk_ij(0, None, None, 10, FAKE, FAKE, FAKE, 0.0, None, None, None,
+                                    None, None, check=False) == _lib.NBODY_OK
+    o = _lib.nbody_opts_default()
+    o.jtile = 100
+    assert _lib.nbody_force_jerk_ij(10, FAKE, FAKE, 10, FAKE, FAKE, FAKE, 0.1, FAKE, FAKE, None,
+                                    o, None, check=False) == _lib.NBODY_EINVAL
+    assert _lib.nbody_workspace_size_jerk_ij(0, 10, None) == 0
+    assert _lib.nbody_workspace_size_jerk_ij(1000, 5000, None) > 0
+
+
 def test_force_jerk_options():
     o = _lib.nbody_opts_default()
     o.centre = 7

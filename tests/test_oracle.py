@@ -253,6 +253,35 @@ def test_jerk_invariants():
     np.testing.assert_array_equal(j_s, jerk[idx])
 
 
+def test_jerk_ij_is_the_time_derivative_of_force_ij():
+    # Separate sets in relative motion (an active subset of one sphere against another
+    # sphere): along x_i + v_i t and x_j + v_j t the jerk is d a_i / dt; central
+    # differences of the (separately pinned) force_ij, h = 1e-5, with eps = 0 as well.
+    xj, vj, mj = ics.plummer(80, seed=37)
+    xi, vi, _ = ics.plummer(20, seed=38)
+    xi = xi * 0.7 + 0.3
+    h = 1e-5
+    for eps in (0.05, 0.0):
+        _, jerk, _ = oracle.force_jerk_ij(xj, vj, mj, xi, vi, eps)
+        ap, _ = oracle.force_ij(xj + h * vj, mj, xi + h * vi, eps)
+        am, _ = oracle.force_ij(xj - h * vj, mj, xi - h * vi, eps)
+        fd = (ap - am) / (2 * h)
+        assert rel_errors(jerk, fd)["normwise"] < 1e-7, eps
+
+
+def test_jerk_ij_on_one_set_matches_force_jerk():
+    # With the i-set equal to the j-set the only difference from the single-set sum is
+    # the j == i pair: it adds exactly zero to a and the jerk and -m_i/eps to phi.
+    x, v, m = ics.plummer(300, seed=39)
+    m = m * np.random.default_rng(40).uniform(0.5, 1.5, m.size)
+    eps = 0.03
+    a1, j1, p1 = oracle.force_jerk(x, v, m, eps)
+    a2, j2, p2 = oracle.force_jerk_ij(x, v, m, x, v, eps)
+    np.testing.assert_array_equal(a2, a1)
+    np.testing.assert_array_equal(j2, j1)
+    np.testing.assert_allclose(p2, p1 - m / eps, rtol=1e-13)
+
+
 # --------------------------------------------------------------------------- mean field
 def test_shell_theorem_on_plummer_realisation():
     # For a near-spherical particle set the shell-averaged field at radius r is that of
