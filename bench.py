@@ -22,6 +22,9 @@ step evaluates):
   shard8_131072  one GPU's share of an 8-way i-split of the N = 131072 sphere: force and
                  potential on 16384 i-particles from all 131072 (separate i- and j-sets);
                  step = one evaluation.
+  active8_131072 a seeded eighth (16384) of the N = 131072 sphere as the active set of a
+                 Hermite code with individual steps: step = one force+jerk+potential
+                 evaluation of those particles from all 131072 (separate i- and j-sets).
   jerk_131072    the N = 131072 sphere; step = one graph-replayed fourth-order Hermite
                  step (dt = 1/256): FP64 predictor, one N^2 force+jerk evaluation from
                  the predicted state, FP64 corrector.
@@ -141,7 +144,8 @@ def parse():
                          "about %.2f s, at least 2)" % WARM_SECONDS)
     ap.add_argument("--workload", default="plummer_131072",
                     choices=["plummer_131072", "plummer_2048", "stress_1m", "clusters_2048",
-                             "adjoint_16384", "jerk_131072", "shard8_131072"])
+                             "adjoint_16384", "jerk_131072", "shard8_131072",
+                             "active8_131072"])
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the FP64 oracle leg (no errors, no CPU rate)")
     ap.add_argument("--cpu-sample", type=int, default=0,
@@ -714,6 +718,87 @@ def bench_jerk(args, torch, w):
     }
 
 
+def bench_active(args, torch, w):
+    """Force + jerk + potential of the active eighth of the N = 131072 sphere (a seeded
+    sample of 16384 particles, as a Hermite code with individual steps would evaluate)
+    from all 131072: one nbody_force_jerk_ij call per step."""
+    from paper_astro_ph_0703100_amd import _lib, api, ics, metrics
+    n, ni = w.n, w.n // 8
+    pos, vel, mass = ics.plummer(n, seed=w.seed)
+    act = ics.sample_indices(n, ni, seed=w.seed + 3000)
+    m32 = mass.astype(np.float32)
+    eps = float(np.float32(w.eps))
+    dev = torch.device("cuda:0")
+    p32 = np.ascontiguousarray(pos.T.astype(np.float32))
+    v32 = np.ascontiguousarray(vel.T.astype(np.float32))
+    pj, vj = torch.from_numpy(p32).to(dev), torch.from_numpy(v32).to(dev)
+    pi = torch.from_numpy(np.ascontiguousarray(p32[:, act])).to(dev)
+    vi = torch.from_numpy(np.ascontiguousarray(v32[:, act])).to(dev)
+    m = torch.from_numpy(m32).to(dev)
+    acc = torch.empty((3, ni), dtype=torch.float64, device=dev)
+    jerk = torch.empty((3, ni), dtype=torch.float64, device=dev)
+    pot = torch.empty(ni, dtype=torch.float64, device=dev)
+    sp = torch.cuda.current_stream().cuda_stream
+    timer = Timer(torch)
+    pairs = float(ni) * float(n)
+    res = {}
+    for precision in [s for s in args.modes.split(",") if s]:
+        opts = api.make_opts(precision=precision)
+        call = lambda: _lib.nbody_force_jerk_ij(ni, pi.data_ptr(), vi.data_ptr(), n, pj.data_ptr(),
+                                                vj.data_ptr(), m.data_ptr(), eps, acc.data_ptr(),
+                                                jerk.data_ptr(), pot.data_ptr(), opts, sp)
+        wall, kms = timer.run(call, args.steps, warmup=args.warmup)
+        res[precision] = {"wall": wall, "kernel_ms": float(np.mean(kms)),
+                          "out": (acc.cpu().numpy().T.copy(), jerk.cpu().numpy().T.copy(),
+                                  pot.cpu().numpy().copy())}
+        print("bench: %-8s %d evaluations  %.3f ms each (wall)  %.3f ms (events)"
+              % (precision, args.steps, wall / args.steps * 1e3, np.mean(kms)),
+              file=sys.stderr, flush=True)
+    cpu, errors = None, {}
+    if not args.no_cpu_baseline:
+        import oracle
+        k = ni if args.cpu_sample <= 0 else min(ni, args.cpu_sample)
+        x64, v64 = p32.T.astype(np.float64), v32.T.astype(np.float64)
+        mj = m32.astype(np.float64)
+        sel = act[:k]
+        t0 = time.perf_counter()
+        ra, rj, rp = oracle.force_jerk_ij(x64, v64, mj, x64[sel], v64[sel], eps)
+        ct = time.perf_counter() - t0
+        cpu = {"value": k * float(n) / ct, "unit": "pair-interactions/s",
+               "cores": oracle.threads(), "kind": "oracle",
+               "sample": "force+jerk+potential of %d of the active particles from all %d, FP64 "
+                         "(%.1f s)" % (k, n, ct)}
+        s1 = sel[::16]
+        one_thread(cpu, lambda: oracle.force_jerk_ij(x64, v64, mj, x64[s1], v64[s1], eps),
+                   float(s1.size) * n, "%d of those i-particles" % s1.size)
+        for p, r in res.items():
+            a, j, ph = r["out"]
+            e = errors_of(metrics, a[:k], ph[:k], ra, rp)
+            ej = metrics.rel_errors(j[:k], rj)
+            e.update({"jerk_rel_rms": ej["rel_rms"], "jerk_e_max": ej["e_max"],
+                      "jerk_normwise": ej["normwise"]})
+            errors[p] = e
+    head = next(iter(res))
+    r0 = res[head]
+    return {
+        "value": pairs * args.steps / r0["wall"], "ms_per_step": r0["wall"] / args.steps * 1e3,
+        "config": {"workload": w.name, "n": n, "n_i": ni, "eps": eps, "seed": w.seed,
+                   "precision": head,
+                   "step": "one force+jerk+potential evaluation of 16384 active particles (a "
+                           "seeded sample) from all 131072 (nbody_force_jerk_ij, FP32 inputs); "
+                           "the active particles' own pairs count as for any separate i-set",
+                   "description": w.description},
+        "roofline": roofline("jerk", pairs, r0["kernel_ms"],
+                             "tile_kernel<GravityJerkIJ> (+ jerk_finalize_kernel)"),
+        "cpu_baseline": cpu,
+        "modes": {p: {"value": pairs * args.steps / r["wall"],
+                      "ms_per_step": r["wall"] / args.steps * 1e3,
+                      "kernel_ms": r["kernel_ms"],
+                      "roofline_frac": pairs / (r["kernel_ms"] * 1e-3) / peak_pairs("jerk"),
+                      "errors": errors.get(p)} for p, r in res.items()},
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -740,7 +825,7 @@ def main():
     fn = {"plummer_131072": bench_plummer, "plummer_2048": bench_plummer,
           "stress_1m": bench_stress, "clusters_2048": bench_clusters,
           "adjoint_16384": bench_adjoint, "jerk_131072": bench_jerk,
-          "shard8_131072": bench_shard}[w.name]
+          "shard8_131072": bench_shard, "active8_131072": bench_active}[w.name]
     body = fn(args, torch, w)
     line = {
         "metric": METRIC if w.name == "plummer_131072" else "pair interactions/s, " + w.name,

@@ -252,6 +252,10 @@ WORKLOADS = {
         "shard8_131072", 131072, plummer_131072_eps(131072), 2,
         description="one GPU's share of an 8-way i-split of the N=131072 sphere (same seed "
                     "and eps): 16384 i-particles against all 131072"),
+    "active8_131072": Workload(
+        "active8_131072", 131072, plummer_131072_eps(131072), 2,
+        description="the N=131072 sphere of plummer_131072 (same seed and eps) with "
+                    "velocities; a seeded sample of 16384 active particles against all 131072"),
     "jerk_131072": Workload(
         "jerk_131072", 131072, plummer_131072_eps(131072), 2, dt=1.0 / 256.0, steps=8,
         description="N=131072 Plummer as plummer_131072 (same seed and eps); fourth-order "
