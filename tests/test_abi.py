@@ -249,6 +249,41 @@ def test_vjp_and_adjoint_reject_invalid_arguments():
     assert adj(0, None, None, 0.1, 0.01, 2, None, None, None, o, None, check=False) == _lib.NBODY_OK
 
 
+@pytest.mark.parametrize("nsys,offsets,opt,status,what", [
+    (-1, [0], {}, "NBODY_EINVAL", "negative nsys"),
+    (2, [1, 5, 9], {}, "NBODY_EINVAL", "offsets[0] != 0"),
+    (3, [0, 5, 4, 9], {}, "NBODY_EINVAL", "decreasing offsets"),
+    (1, [0, 1 << 31], {}, "NBODY_EINVAL", "too many particles"),
+    (2, [0, 5, 9], {"precision": 4}, "NBODY_EINVAL", "bad precision"),
+    (2, [0, 5, 9], {"ipl": 3}, "NBODY_EINVAL", "bad ipl"),
+    (2, [0, 5, 9], {"jtile": 32}, "NBODY_EINVAL", "bad jtile"),
+    (2, [0, 5, 9], {"centre": 2}, "NBODY_EUNSUPPORTED", "tile centres"),
+    (2, [0, 5, 9], {"self_pot": 1}, "NBODY_EUNSUPPORTED", "self term kept"),
+])
+def test_batched_plan_rejects_bad_offsets_and_options(nsys, offsets, opt, status, what):
+    # Checked on the host before any device call; the plan handle stays NULL.
+    o = _lib.nbody_opts_default()
+    for k, v in opt.items():
+        setattr(o, k, v)
+    arr = (ctypes.c_int64 * max(1, len(offsets)))(*offsets)
+    h = ctypes.c_void_p(12345)
+    st = _lib.load().nbody_plan_create_batched(nsys, arr, ctypes.byref(o), ctypes.byref(h))
+    assert st == getattr(_lib, status), what
+    assert h.value is None, what
+    assert _lib.nbody_last_error() != ""
+
+
+def test_batched_plan_rejects_a_caller_workspace():
+    o = _lib.nbody_opts_default()
+    o.workspace = FAKE
+    o.workspace_bytes = 1 << 20
+    arr = (ctypes.c_int64 * 3)(0, 5, 9)
+    h = ctypes.c_void_p()
+    assert _lib.load().nbody_plan_create_batched(2, arr, ctypes.byref(o), ctypes.byref(h)) == \
+        _lib.NBODY_EINVAL
+    assert _lib.load().nbody_plan_create_batched(2, arr, None, None) == _lib.NBODY_EINVAL
+
+
 def test_tuning_table_roundtrip(tmp_path):
     _lib.nbody_tune_reset()
     base = _lib.nbody_tune_get(_lib.NBODY_KERNEL_FORCE, _lib.NBODY_COMP, 131072)

@@ -4,6 +4,8 @@ The library runs asynchronously on the caller's stream; with a caller workspace 
 enqueues nothing but kernel launches, so a caller can record it into a HIP graph and
 run independent evaluations on several streams at once.
 """
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -77,3 +79,28 @@ def test_caller_graph_capture_replays_match_eager():
     torch.cuda.synchronize()
     assert torch.equal(acc, acc_direct)
     assert not torch.equal(acc, ref_acc)
+
+
+def test_graph_creation_refuses_a_capturing_stream():
+    # The library's own graphs capture on a private stream; asked to build one on a stream
+    # the caller is already capturing, it returns NBODY_ECAPTURE and launches nothing, and
+    # the caller's capture stays valid.
+    n, eps = 4096, 0.02
+    p, m = system(n, 84)
+    x = p.double().contiguous()
+    v = torch.zeros_like(x)
+    acc = torch.empty((3, n), dtype=torch.float64, device=DEV)
+    ones = torch.ones(16, device=DEV)
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        ones.add_(1.0)
+        h = ctypes.c_void_p()
+        st = _lib.load().nbody_graph_create_leapfrog(
+            n, x.data_ptr(), v.data_ptr(), m.data_ptr(), eps, 1.0 / 256, 1, acc.data_ptr(),
+            None, None, s.cuda_stream, ctypes.byref(h))
+    assert st == _lib.NBODY_ECAPTURE and h.value is None
+    g.replay()
+    torch.cuda.synchronize()
+    assert torch.all(ones == 2.0)
