@@ -101,6 +101,37 @@ def test_batched_is_deterministic_and_f64_path_matches():
     plan.close()
 
 
+@pytest.mark.parametrize("precision,ipl,jtile", [("comp", 1, 64), ("fp64red", 2, 256),
+                                                  ("plain", 1, 128)])
+def test_batched_equals_single_system_calls_bitwise(precision, ipl, jtile):
+    # A plan splits system k into i-tiles and S_k j-segments of about 4096 j's; the
+    # single-system entry point at the same IPL, j-tile and S_k runs the same blocks and
+    # the same fixed-order reduction, so every system's result is the same bits.
+    sizes = [5000, 300, 9000, 0, 1, 4097, 64]
+    offsets, pos, _, m32, eps = ragged(sizes, seed=400, eps_list=[0.01, 0.02, 0.005, 0.01,
+                                                                  0.01, 0.03, 0.01])
+    plan = api.BatchPlan(offsets, precision=precision, ipl=ipl, jtile=jtile)
+    p = torch.from_numpy(np.ascontiguousarray(pos.T.astype(np.float32))).to(DEV)
+    m = torch.from_numpy(m32).to(DEV)
+    acc, pot = plan.force(p, m, torch.from_numpy(eps).to(DEV))
+    torch.cuda.synchronize()
+    per_seg_tiles = max(1, 4096 // jtile)
+    for k, n in enumerate(sizes):
+        if n < 2:
+            continue
+        s, t = int(offsets[k]), int(offsets[k + 1])
+        jtiles = -(-n // jtile)
+        segs = -(-jtiles // per_seg_tiles)
+        per = -(-jtiles // segs)
+        segs = -(-jtiles // per)
+        a1, p1 = api.force(p[:, s:t].contiguous(), m[s:t].contiguous(), float(eps[k]),
+                           precision=precision, ipl=ipl, jtile=jtile, nseg=segs)
+        torch.cuda.synchronize()
+        assert torch.equal(acc[:, s:t], a1), (k, n)
+        assert torch.equal(pot[s:t], p1), (k, n)
+    plan.close()
+
+
 def test_batched_graph_replay_is_bitwise_eager():
     offsets, pos, vel, m32, eps = ragged([3000, 1000, 257, 6000], seed=400)
     plan = api.BatchPlan(offsets)
