@@ -1,4 +1,4 @@
-"""Seeded random launch shapes and sizes for every pair pipeline against the oracle.
+"""Seeded random launch shapes and sizes for the pair pipelines against the oracle.
 
 Each case draws a particle count (ragged against every tile size), a launch shape
 (i-particles per lane, j-tile, j-segments, including more segments than j-tiles), an
@@ -12,7 +12,7 @@ import pytest
 import torch
 
 import oracle
-from paper_astro_ph_0703100_amd import api, ics
+from paper_astro_ph_0703100_amd import _lib, api, ics
 from paper_astro_ph_0703100_amd.metrics import rel_errors
 
 pytestmark = pytest.mark.gpu
@@ -107,3 +107,62 @@ def test_force_jerk(k):
     err = np.sqrt(((jerk.cpu().numpy().T - rj) ** 2).sum(1))
     cmax = 74.0 + (c["n"] + 1024 if c["precision"] == "plain" else min(128, c["jtile"]) - 1)
     assert np.all(err <= cmax * U * scale), (c, float((err / (U * scale)).max()))
+
+
+def scaled_max(approx, exact):
+    return float(np.abs(approx - exact).max() / np.sqrt(np.mean(exact ** 2)))
+
+
+@pytest.mark.parametrize("k", range(0, len(CASES), 2))
+def test_vjp(k):
+    # Tolerances of the adjoint tests: dL/dx relative RMS, dL/dm max error over its RMS
+    # (1e-5 compensated and FP64-reduced, 1e-4 plain FP32).
+    c = CASES[k]
+    n = c["n"]
+    x, _, m = sphere(n, 6000 + k)
+    rng = np.random.default_rng(7000 + k)
+    ga = rng.standard_normal((n, 3)).astype(np.float32).astype(np.float64)
+    gp = rng.standard_normal(n).astype(np.float32).astype(np.float64)
+    gx = torch.empty((3, n), dtype=torch.float64, device=DEV)
+    gm = torch.empty(n, dtype=torch.float64, device=DEV)
+    opts = api.make_opts(precision=c["precision"], ipl=c["ipl"], jtile=c["jtile"], nseg=c["nseg"])
+    # Keep every input tensor referenced until the call is done: a temporary freed after
+    # its data_ptr() is read can be handed to the next allocation.
+    p, mm = t32(x), torch.from_numpy(m.astype(np.float32)).to(DEV)
+    g, gpt = torch.from_numpy(np.ascontiguousarray(ga.T)).to(DEV), torch.from_numpy(gp).to(DEV)
+    _lib.nbody_force_vjp(n, p.data_ptr(), mm.data_ptr(), c["eps"], g.data_ptr(), gpt.data_ptr(),
+                         gx.data_ptr(), gm.data_ptr(), opts, api.stream_ptr())
+    torch.cuda.synchronize()
+    rx, rm = oracle.vjp(x, m, c["eps"], ga, gp)
+    tol = 1e-4 if c["precision"] == "plain" else 1e-5
+    if n > 1:
+        assert rel_errors(gx.cpu().numpy().T, rx)["rel_rms"] <= tol, c
+        assert scaled_max(gm.cpu().numpy(), rm) <= tol, c
+
+
+@pytest.mark.parametrize("k", range(1, len(CASES), 2))
+def test_force_jerk_ij(k):
+    c = CASES[k]
+    ni = max(1, c["n"] // 5)
+    xi, vi, _ = sphere(ni, 8000 + k)
+    xj, vj, mj = sphere(c["n"], 9000 + k)
+    xi = xi * 1.2 + 0.02
+    shape = dict(ipl=c["ipl"], jtile=c["jtile"], nseg=c["nseg"])
+    acc, jerk, pot = api.force_jerk_ij(t32(xi), t32(vi), t32(xj), t32(vj),
+                                       torch.from_numpy(mj.astype(np.float32)).to(DEV), c["eps"],
+                                       precision=c["precision"], **shape)
+    torch.cuda.synchronize()
+    ra, rj, rp = oracle.force_jerk_ij(xj, vj, mj, xi, vi, c["eps"])
+    assert rel_errors(acc.cpu().numpy().T, ra)["rel_rms"] <= TOL[c["precision"]], c
+    assert rel_errors(pot.cpu().numpy(), rp)["rel_rms"] <= TOL[c["precision"]], c
+    e2 = c["eps"] ** 2
+    scale = np.empty(ni)
+    for i in range(ni):
+        d, w = xj - xi[i], vj - vi[i]
+        s2 = (d * d).sum(1) + e2
+        dn = np.sqrt((d * d).sum(1))
+        scale[i] = (mj * (np.sqrt((w * w).sum(1)) / s2 ** 1.5
+                          + 3 * np.abs((d * w).sum(1)) * dn / s2 ** 2.5)).sum()
+    err = np.sqrt(((jerk.cpu().numpy().T - rj) ** 2).sum(1))
+    cmax = 74.0 + (c["n"] + 1024 if c["precision"] == "plain" else min(128, c["jtile"]) - 1)
+    assert np.all(err <= cmax * U * scale), (c, float((err / (U * scale + 1e-300)).max()))
