@@ -3,6 +3,12 @@
 Argument marshalling only: every function here forwards plain integers, floats
 and device addresses to the C ABI and returns its status.  The library is loaded
 on first use; if it has not been built this raises (there is no fallback).
+
+The calls are asynchronous on the given stream and read and write the arrays
+behind the addresses later.  A caller passing ``tensor.data_ptr()`` must hold a
+reference to every such tensor until the call has returned: a temporary
+(``t.float().data_ptr()`` inside the argument list) can be freed, and its memory
+handed to the next allocation, before the library has even enqueued its kernels.
 """
 from __future__ import annotations
 
