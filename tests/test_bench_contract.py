@@ -2,6 +2,7 @@
 import json
 import os
 import subprocess
+import time
 import sys
 
 import pytest
@@ -48,3 +49,26 @@ def test_sources_hash_ignores_comments_only():
     assert bench.code_text(src) == bench.code_text(src.replace("u m / eps", "A u (m / eps)"))
     assert bench.code_text(src) != bench.code_text(src.replace("a / b", "a * b"))
     assert '"//kept"' in bench.code_text(src)
+
+
+def test_warm_up_fills_its_time_budget_or_the_given_count():
+    class FakeCuda:
+        @staticmethod
+        def synchronize():
+            pass
+
+    class FakeTorch:
+        cuda = FakeCuda
+
+    calls = []
+
+    def call():
+        calls.append(1)
+        time.sleep(0.01)
+
+    k = bench.warm_up(FakeTorch, call, None)
+    assert k == len(calls) and bench.WARMED[-1] == k
+    assert k >= 2 and 0.8 * bench.WARM_SECONDS <= 0.01 * k <= 2.0 * bench.WARM_SECONDS
+    calls.clear()
+    assert bench.warm_up(FakeTorch, call, 3) == 3 and len(calls) == 3
+    assert bench.warm_up(FakeTorch, call, 0) == 0
