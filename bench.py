@@ -80,10 +80,11 @@ FLOPS = {"gravity": 20, "jerk": 60, "adjoint": 45}
 # Kernel sources behind the committed counter summaries, and the tuning file whose
 # force-kernel entries for N = 131072 (size bucket 17) pick the launch shape (traffic is
 # dropped when either changes).
+# The files that define the pair kernel tile_kernel<Gravity> (force.hip only instantiates
+# it; its own kernels are the finalize and centre passes).
 KERNEL_SOURCES = ["paper_astro_ph_0703100_amd/csrc/nbody_internal.h",
                   "paper_astro_ph_0703100_amd/csrc/tile_engine.h",
-                  "paper_astro_ph_0703100_amd/csrc/gravity.h",
-                  "paper_astro_ph_0703100_amd/csrc/force.hip"]
+                  "paper_astro_ph_0703100_amd/csrc/gravity.h"]
 TUNING_FILE = "paper_astro_ph_0703100_amd/tuning_gfx950.json"
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "pair_kernel_plummer_131072.md")
 

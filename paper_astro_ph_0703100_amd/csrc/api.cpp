@@ -216,7 +216,8 @@ nbody_status force_f32_core(int64_t n, const float *pos, const float *mass, floa
 
 nbody_status force_f64_core(int64_t n, const double *pos64, const float *mass, float eps,
                             double *acc, double *pot, const nbody_opts &o, const TileCfg &cfg,
-                            const F64Scratch &ws, double *kick_v, double kick_h, hipStream_t s) {
+                            const F64Scratch &ws, double *kick_v, double kick_h, hipStream_t s,
+                            bool centre_ready) {
     nbody_status st;
     if (o.centre == NBODY_CENTRE_TILE) {
         // Per-i-tile centres (3 doubles per tile fit in the FP32-position area, which this
@@ -233,7 +234,9 @@ nbody_status force_f64_core(int64_t n, const double *pos64, const float *mass, f
         return launch_finalize(o.precision, fa, s);
     }
     if (o.centre == NBODY_CENTRE_SYSTEM) {
-        if ((st = launch_centred_convert(n, pos64, ws.centre_scratch, ws.x32, s))) return st;
+        st = centre_ready ? launch_centred_convert_ready(n, pos64, ws.centre_scratch, ws.x32, s)
+                          : launch_centred_convert(n, pos64, ws.centre_scratch, ws.x32, s);
+        if (st) return st;
     } else {
         if ((st = launch_convert(n, pos64, nullptr, ws.x32, s))) return st;
     }

@@ -37,7 +37,6 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinalizeArgs a) {
 
 // Two-stage fixed-order FP64 mean of the positions [3][n]: kCentreBlocks partial
 // sums, then their fixed-order sum.  Deterministic for a given n.
-constexpr int kCentreBlocks = 256;
 
 __global__ __launch_bounds__(256) void centre_partial_kernel(int64_t n, const double *pos,
                                                             double *part) {
@@ -174,6 +173,15 @@ nbody_status launch_centred_convert(int64_t n, const double *pos64, double *scra
     NBODY_HIP_CHECK(hipGetLastError());
     hipLaunchKernelGGL(centred_convert_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
                        n, pos64, (const double *)scratch, pos32);
+    NBODY_HIP_CHECK(hipGetLastError());
+    return NBODY_OK;
+}
+
+nbody_status launch_centred_convert_ready(int64_t n, const double *pos64, const double *scratch,
+                                          float *pos32, hipStream_t s) {
+    if (n <= 0) return NBODY_OK;
+    hipLaunchKernelGGL(centred_convert_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                       n, pos64, scratch, pos32);
     NBODY_HIP_CHECK(hipGetLastError());
     return NBODY_OK;
 }

@@ -43,9 +43,14 @@ nbody_status enqueue_steps(int64_t n, double *x, double *v, const float *m, floa
     if (traj && (st = launch_copy_f64((int64_t)n3, x, traj, s))) return st;
     for (int32_t t = 0; t < nsteps; ++t) {
         double *checkpoint = traj ? traj + (size_t)(t + 1) * n3 : nullptr;
-        if ((st = launch_kick_drift(n, x, v, acc, 0.5 * dt, dt, s, checkpoint))) return st;
+        // With the system centre, the kick-drift also sums the new positions for it.
+        const bool fused = o.centre == NBODY_CENTRE_SYSTEM;
+        st = fused ? launch_kick_drift_centre(n, x, v, acc, 0.5 * dt, dt, checkpoint,
+                                              ws.centre_scratch, s)
+                   : launch_kick_drift(n, x, v, acc, 0.5 * dt, dt, s, checkpoint);
+        if (st) return st;
         if ((st = force_f64_core(n, x, m, eps, acc, t + 1 == nsteps ? pot : nullptr, o, cfg, ws, v,
-                                 0.5 * dt, s)))
+                                 0.5 * dt, s, fused)))
             return st;
     }
     return NBODY_OK;

@@ -20,6 +20,38 @@ __global__ __launch_bounds__(256) void kick_drift_kernel(int64_t count, double *
     if (checkpoint) checkpoint[q] = xx;
 }
 
+// The kick and drift of kick_drift_kernel on a fixed grid of kCentreBlocks blocks that
+// stride over the particles exactly as the centre's first stage does, summing each
+// thread's new positions in that order and reducing them with the same tree: the
+// partials are bitwise those of a separate pass over the new positions.
+__global__ __launch_bounds__(256) void kick_drift_centre_kernel(
+    int64_t n, double *__restrict__ x, double *__restrict__ v, const double *__restrict__ a,
+    double h, double dt, double *__restrict__ checkpoint, double *__restrict__ part) {
+    __shared__ double sh[3][256];
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int64_t q = c * n + i;
+            const double vv = v[q] + h * a[q];
+            v[q] = vv;
+            const double xx = x[q] + dt * vv;
+            x[q] = xx;
+            if (checkpoint) checkpoint[q] = xx;
+            s[c] += xx;
+        }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) sh[c][threadIdx.x] = s[c];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) sh[c][threadIdx.x] += sh[c][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) part[blockIdx.x * 3 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
 __global__ __launch_bounds__(256) void kick_kernel(int64_t count, double *__restrict__ v,
                                                   const double *__restrict__ a, double h) {
     const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -68,6 +100,16 @@ nbody_status launch_kick_drift(int64_t n, double *x, double *v, const double *ac
     if (n <= 0) return NBODY_OK;
     hipLaunchKernelGGL(kick_drift_kernel, grid_for(3 * n), dim3(256), 0, s, 3 * n, x, v, acc, h, dt,
                        checkpoint);
+    NBODY_HIP_CHECK(hipGetLastError());
+    return NBODY_OK;
+}
+
+nbody_status launch_kick_drift_centre(int64_t n, double *x, double *v, const double *acc,
+                                      double h, double dt, double *checkpoint,
+                                      double *centre_part, hipStream_t s) {
+    if (n <= 0) return NBODY_OK;
+    hipLaunchKernelGGL(kick_drift_centre_kernel, dim3(kCentreBlocks), dim3(256), 0, s, n, x, v, acc,
+                       h, dt, checkpoint, centre_part);
     NBODY_HIP_CHECK(hipGetLastError());
     return NBODY_OK;
 }

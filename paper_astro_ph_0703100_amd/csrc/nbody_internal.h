@@ -25,6 +25,8 @@ namespace nbody {
 constexpr int kTPB = 256;
 // Largest number of j-segments a launch may split the j range into.
 constexpr int kMaxSeg = 1024;
+// Blocks of the first stage of the FP64 system centre (fixed, so the sum order is too).
+constexpr int kCentreBlocks = 256;
 // Default number of j's summed in plain FP32 between two compensation / FP64 steps; a
 // pipeline may set its own (Op::kBlockJ), and the engine caps it at the j-tile.  128
 // keeps the two-sums under 0.6 VALU operations per pair for every pipeline (force:
@@ -265,9 +267,12 @@ F64Scratch f64_scratch_layout(void *ws, int64_t n, const TileCfg &cfg, int preci
 
 // One force evaluation from FP64 positions: centre + conversion (per opts.centre),
 // pair kernel, FP64 finalize (optionally followed by v += kick_h * a).
+// centre_ready: with NBODY_CENTRE_SYSTEM, the first stage of the centre is already in
+// ws.centre_scratch (launch_kick_drift_centre wrote it for these positions).
 nbody_status force_f64_core(int64_t n, const double *pos64, const float *mass, float eps,
                             double *acc, double *pot, const nbody_opts &o, const TileCfg &cfg,
-                            const F64Scratch &ws, double *kick_v, double kick_h, hipStream_t s);
+                            const F64Scratch &ws, double *kick_v, double kick_h, hipStream_t s,
+                            bool centre_ready = false);
 
 // Records the launches `body` enqueues on a capture stream into g->graph and
 // instantiates g->exec (integrate.cpp).
@@ -290,6 +295,10 @@ nbody_status launch_pair_ij(const TileCfg &cfg, int precision, bool with_pot, co
 // then a fused fixed-order final sum and conversion); scratch holds the partials.
 nbody_status launch_centred_convert(int64_t n, const double *pos64, double *scratch,
                                     float *pos32, hipStream_t s);
+// The second stage alone, for partials already in `scratch` (written by
+// launch_kick_drift_centre).
+nbody_status launch_centred_convert_ready(int64_t n, const double *pos64, const double *scratch,
+                                          float *pos32, hipStream_t s);
 nbody_status launch_convert(int64_t n, const double *pos64, const double *centre, float *pos32,
                             hipStream_t s);
 // Bytes of the centre-reduction scratch (partials of the two-stage FP64 sum).
@@ -308,6 +317,12 @@ size_t morton_scratch_bytes(int64_t n);
 // v += h a; x += dt v (and checkpoint = x when checkpoint is not null).
 nbody_status launch_kick_drift(int64_t n, double *x, double *v, const double *acc, double h,
                                double dt, hipStream_t s, double *checkpoint = nullptr);
+// The same kick and drift, fused with the first stage of the FP64 centre of the new
+// positions: writes the kCentreBlocks x 3 partials launch_centred_convert computes, in
+// the same order, to `centre_part`.
+nbody_status launch_kick_drift_centre(int64_t n, double *x, double *v, const double *acc,
+                                      double h, double dt, double *checkpoint,
+                                      double *centre_part, hipStream_t s);
 nbody_status launch_kick(int64_t n, double *v, const double *acc, double h, hipStream_t s);
 nbody_status launch_copy_f64(int64_t count, const double *src, double *dst, hipStream_t s);
 nbody_status launch_fill_f64(int64_t count, double *dst, double value, hipStream_t s);

@@ -47,6 +47,28 @@ def test_leapfrog_matches_oracle_rollout():
     assert rel_errors(pot.cpu().numpy(), po)["rel_rms"] < 1e-6
 
 
+@pytest.mark.parametrize("n", [1, 300, 65536 + 77, 200000])
+def test_step_force_equals_a_separate_evaluation(n):
+    # The kick-drift of a step also sums the new positions for the system centre (in the
+    # order of the centre's own first stage), so the step's acceleration and potential
+    # are bitwise those of nbody_force_f64 on the positions the step produced, and the
+    # kick-drift itself is the plain one (the same positions after one step as with no
+    # centre, where the velocities then differ by the other force rounding).
+    eps, dt = 0.01, 1.0 / 256
+    x, v, m, *_ = state(n, seed=20 + n % 7)
+    acc0, _, _ = api.leapfrog(x.clone(), v.clone(), m, eps, dt, 0)
+    xs, vs, acs = x.clone(), v.clone(), acc0.clone()
+    acc, pot, _ = api.leapfrog(xs, vs, m, eps, dt, 2, acc=acs, init=False, with_pot=True)
+    ref_a, ref_p = api.force_f64(xs, m, eps)
+    x1, v1, a1 = x.clone(), v.clone(), acc0.clone()
+    api.leapfrog(x1, v1, m, eps, dt, 1, acc=a1, init=False)
+    xn, vn, acn = x.clone(), v.clone(), acc0.clone()
+    api.leapfrog(xn, vn, m, eps, dt, 1, acc=acn, init=False, centre="none")
+    torch.cuda.synchronize()
+    assert torch.equal(acc, ref_a) and torch.equal(pot, ref_p)
+    assert torch.equal(x1, xn)
+
+
 def test_graph_replay_is_bitwise_eager():
     n, steps, dt = 5000, 3, 1.0 / 512
     eps = 0.01
