@@ -40,10 +40,13 @@ nbody_status vjp_f32_core(int64_t n, const float *pos, const float *mass, float 
 }
 
 // Centre + FP32 conversion, then the adjoint on the converted positions.
+// centre_ready: with NBODY_CENTRE_SYSTEM, the centre's first stage over pos64 is already
+// in ws.centre_scratch.
 nbody_status vjp_f64_core(int64_t n, const double *pos64, const float *mass, float eps,
                           const double *g_acc, const double *g_pot, double *grad_pos,
                           double *grad_mass, bool accumulate, const nbody_opts &o,
-                          const TileCfg &cfg, const F64Scratch &ws, hipStream_t s) {
+                          const TileCfg &cfg, const F64Scratch &ws, hipStream_t s,
+                          bool centre_ready = false) {
     nbody_status st;
     if (o.centre == NBODY_CENTRE_TILE) {
         // Per-i-tile centres in the FP32-position area (unused in this mode).
@@ -59,7 +62,9 @@ nbody_status vjp_f64_core(int64_t n, const double *pos64, const float *mass, flo
         return launch_vjp_finalize(o.precision, fa, s);
     }
     if (o.centre == NBODY_CENTRE_SYSTEM) {
-        if ((st = launch_centred_convert(n, pos64, ws.centre_scratch, ws.x32, s))) return st;
+        st = centre_ready ? launch_centred_convert_ready(n, pos64, ws.centre_scratch, ws.x32, s)
+                          : launch_centred_convert(n, pos64, ws.centre_scratch, ws.x32, s);
+        if (st) return st;
     } else {
         if ((st = launch_convert(n, pos64, nullptr, ws.x32, s))) return st;
     }
@@ -140,15 +145,24 @@ nbody_status nbody_leapfrog_adjoint(int64_t n, const double *traj, const float *
     // abar = dt vbar; the last state's a is used by one kick only.
     if ((st = launch_fill_f64((int64_t)n3, abar, 0.0, s))) return st;
     if ((st = launch_axpy_f64((int64_t)n3, abar, h, vbar, s))) return st;
+    // With the system centre, each drift-kick update also runs the centre's first stage
+    // over the checkpoint the next adjoint evaluation reads.
+    const bool fused = o.centre == NBODY_CENTRE_SYSTEM;
+    bool ready = false;
     for (int32_t t = nsteps - 1; t >= 0; --t) {
         const double *x1 = traj + (size_t)(t + 1) * n3;
-        if ((st = vjp_f64_core(n, x1, mass, eps, abar, nullptr, xbar, mbar, true, o, cfg, lay, s)))
+        if ((st = vjp_f64_core(n, x1, mass, eps, abar, nullptr, xbar, mbar, true, o, cfg, lay, s,
+                               ready)))
             return st;
         // drift of step t (vbar += dt xbar), then both kicks that use a(x_t)
-        if ((st = launch_adj_drift_kick((int64_t)n3, vbar, xbar, abar, dt, t > 0 ? dt : h, s)))
-            return st;
+        const double hk = t > 0 ? dt : h;
+        st = fused ? launch_adj_drift_kick_centre(n, vbar, xbar, abar, dt, hk, traj + (size_t)t * n3,
+                                                  lay.centre_scratch, s)
+                   : launch_adj_drift_kick((int64_t)n3, vbar, xbar, abar, dt, hk, s);
+        if (st) return st;
+        ready = fused;
     }
-    return vjp_f64_core(n, traj, mass, eps, abar, nullptr, xbar, mbar, true, o, cfg, lay, s);
+    return vjp_f64_core(n, traj, mass, eps, abar, nullptr, xbar, mbar, true, o, cfg, lay, s, ready);
 }
 
 }  // extern "C"

@@ -91,6 +91,36 @@ __global__ __launch_bounds__(256) void adj_drift_kick_kernel(int64_t count, doub
     abar[q] = h * vb;
 }
 
+// adj_drift_kick_kernel on the centre's fixed grid, fused with the centre's first stage
+// over `next` (the checkpoint the following adjoint evaluation reads), in the order and
+// tree of the separate pass.
+__global__ __launch_bounds__(256) void adj_drift_kick_centre_kernel(
+    int64_t n, double *__restrict__ vbar, const double *__restrict__ xbar,
+    double *__restrict__ abar, double dt, double h, const double *__restrict__ next,
+    double *__restrict__ part) {
+    __shared__ double sh[3][256];
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int64_t q = c * n + i;
+            const double vb = vbar[q] + dt * xbar[q];
+            vbar[q] = vb;
+            abar[q] = h * vb;
+            s[c] += next[q];
+        }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) sh[c][threadIdx.x] = s[c];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) sh[c][threadIdx.x] += sh[c][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) part[blockIdx.x * 3 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
 dim3 grid_for(int64_t count) { return dim3((unsigned)((count + 255) / 256)); }
 
 }  // namespace
@@ -147,6 +177,16 @@ nbody_status launch_adj_drift_kick(int64_t count, double *vbar, const double *xb
     if (count <= 0) return NBODY_OK;
     hipLaunchKernelGGL(adj_drift_kick_kernel, grid_for(count), dim3(256), 0, s, count, vbar, xbar,
                        abar, dt, h);
+    NBODY_HIP_CHECK(hipGetLastError());
+    return NBODY_OK;
+}
+
+nbody_status launch_adj_drift_kick_centre(int64_t n, double *vbar, const double *xbar, double *abar,
+                                          double dt, double h, const double *next,
+                                          double *centre_part, hipStream_t s) {
+    if (n <= 0) return NBODY_OK;
+    hipLaunchKernelGGL(adj_drift_kick_centre_kernel, dim3(kCentreBlocks), dim3(256), 0, s, n, vbar,
+                       xbar, abar, dt, h, next, centre_part);
     NBODY_HIP_CHECK(hipGetLastError());
     return NBODY_OK;
 }

@@ -331,6 +331,11 @@ nbody_status launch_axpy_f64(int64_t count, double *y, double alpha, const doubl
 // Reverse of one leapfrog step's drift and first kick: vbar += dt * xbar; abar = h * vbar.
 nbody_status launch_adj_drift_kick(int64_t count, double *vbar, const double *xbar, double *abar,
                                    double dt, double h, hipStream_t s);
+// The same update of the 3n-vectors, fused with the centre's first stage over `next`
+// (partials to `centre_part`, as launch_centred_convert computes them).
+nbody_status launch_adj_drift_kick_centre(int64_t n, double *vbar, const double *xbar, double *abar,
+                                          double dt, double h, const double *next,
+                                          double *centre_part, hipStream_t s);
 // Ragged batches (batched.hip).
 nbody_status batched_pair_kernel(int ipl, int jt, int precision, bool with_pot, const void **fn);
 nbody_status launch_batched_pair(int ipl, int jt, int precision, bool with_pot, int grid,
