@@ -1,0 +1,147 @@
+// Adjoint pipelines for the tile engine (device code, included by the .hip files that
+// launch them): vector-Jacobian product of the softened accelerations and potentials
+// (eq. (1) and the potential of Appendix A) with respect to positions and masses.
+//
+// With d = x_j - x_k, s^2 = |d|^2 + eps^2, cotangents g = dL/da and p = dL/dphi,
+// and K_kj = I/s^3 - 3 d d^T / s^5, differentiating the two sums term by term gives
+//   dL/dx_k =  sum_{j != k} [ K_kj w_kj - d (m_k p_j + m_j p_k) / s^3 ],
+//              w_kj = m_k g_j - m_j g_k
+//           =  sum_{j != k} [ w / s^3 - (q / s^3 + 3 (d . w) / s^5) d ],  q = m_k p_j + m_j p_k
+//   dL/dm_k = -sum_{j != k} [ (g_j . d) / s^3 + p_j / s ].
+// For j == k, d = 0 exactly and w is the difference of two identically rounded
+// products (no FMA contraction), so that pair adds exactly zero to dL/dx_k; its term
+// fl(p_k rsq(eps^2)) in dL/dm_k is rounded on its own and removed exactly in the FP64
+// finalize (the rounding it caused inside an FP32 block partial is at most about
+// kBlockJ u (|p_k| / eps + sum_j |p_j| / s)).
+// 38 VALU operations and one v_rsq_f32 per pair.
+#pragma once
+
+#include "tile_engine.h"
+
+namespace nbody {
+
+namespace {
+
+struct Adjoint {
+    static constexpr int kJWords = 8;  // x, y, z, m, gx, gy, gz, p
+    static constexpr int kOut = 4;     // dL/dx (3) and the positive sum of dL/dm
+    // 128 j's per compensation step (32 before: 1.8 % slower at N = 16384 and 131072).
+    static constexpr int kBlockJ = nbody::kBlockJ;
+    using Args = VjpArgs;
+    struct IState {
+        float x, y, z, m, gx, gy, gz, p;
+    };
+    struct Ctx {};
+    static __device__ __forceinline__ int n_i(const Args &a) { return a.n; }
+    static __device__ __forceinline__ int n_j(const Args &a) { return a.n; }
+    static __device__ __forceinline__ Ctx make_ctx(const Args &, int) { return {}; }
+    static __device__ __forceinline__ IState load_i(const Args &a, const Ctx &, int i) {
+        return {a.x[i], a.y[i], a.z[i], a.m[i], (float)a.gx[i], (float)a.gy[i], (float)a.gz[i],
+                a.gp ? (float)a.gp[i] : 0.0f};
+    }
+    static __device__ __forceinline__ void load_j(const Args &a, const Ctx &, int j, float (&r)[8]) {
+        r[0] = a.x[j];
+        r[1] = a.y[j];
+        r[2] = a.z[j];
+        r[3] = a.m[j];
+        r[4] = (float)a.gx[j];
+        r[5] = (float)a.gy[j];
+        r[6] = (float)a.gz[j];
+        r[7] = a.gp ? (float)a.gp[j] : 0.0f;
+    }
+    // Massless, cotangent-free particle at the origin: every term below is zero.
+    static __device__ __forceinline__ void pad_j(float (&r)[8]) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) r[c] = 0.0f;
+    }
+
+    template <bool MASS>
+    static __device__ __forceinline__ void pair(const float *j, const IState &k, float eps2,
+                                                float (&acc)[4]) {
+        const float dx = j[0] - k.x;
+        const float dy = j[1] - k.y;
+        const float dz = j[2] - k.z;
+        float s2 = __builtin_fmaf(dx, dx, eps2);
+        s2 = __builtin_fmaf(dy, dy, s2);
+        s2 = __builtin_fmaf(dz, dz, s2);
+        const float r = __builtin_amdgcn_rsqf(s2);
+        const float r2 = r * r;
+        const float r3 = r * r2;
+        const float t3 = r2 * 3.0f;
+        const float r5x3 = r3 * t3;  // 3 / s^5
+        // w = m_k g_j - m_j g_k from separately rounded products.
+        const float p1x = k.m * j[4];
+        const float p1y = k.m * j[5];
+        const float p1z = k.m * j[6];
+        const float p2x = j[3] * k.gx;
+        const float p2y = j[3] * k.gy;
+        const float p2z = j[3] * k.gz;
+        const float wx = p1x - p2x;
+        const float wy = p1y - p2y;
+        const float wz = p1z - p2z;
+        float dw = dx * wx;
+        dw = __builtin_fmaf(dy, wy, dw);
+        dw = __builtin_fmaf(dz, wz, dw);
+        const float mp = j[3] * k.p;
+        const float q = __builtin_fmaf(k.m, j[7], mp);
+        const float c3 = r5x3 * dw;
+        const float e = __builtin_fmaf(r3, q, c3);
+        acc[0] = __builtin_fmaf(r3, wx, acc[0]);
+        acc[1] = __builtin_fmaf(r3, wy, acc[1]);
+        acc[2] = __builtin_fmaf(r3, wz, acc[2]);
+        acc[0] = __builtin_fmaf(-e, dx, acc[0]);
+        acc[1] = __builtin_fmaf(-e, dy, acc[1]);
+        acc[2] = __builtin_fmaf(-e, dz, acc[2]);
+        if (MASS) {
+            float gd = j[4] * dx;
+            gd = __builtin_fmaf(j[5], dy, gd);
+            gd = __builtin_fmaf(j[6], dz, gd);
+            const float pr = j[7] * r;  // rounded on its own: its j == k value is removed exactly
+            acc[3] = __builtin_fmaf(gd, r3, acc[3]);
+            acc[3] = acc[3] + pr;
+        }
+    }
+};
+
+// The same on FP64 positions relative to the block's i-tile centre: i's and staged j's
+// are converted as fp32(x - c_I) while loaded (for j == k the two conversions are the
+// same operation, so d = 0 exactly).
+struct AdjointTile {
+    static constexpr int kJWords = 8;
+    static constexpr int kOut = 4;
+    static constexpr int kBlockJ = Adjoint::kBlockJ;
+    using Args = VjpTileArgs;
+    using IState = Adjoint::IState;
+    struct Ctx {
+        double cx, cy, cz;
+    };
+    static __device__ __forceinline__ int n_i(const Args &a) { return a.n; }
+    static __device__ __forceinline__ int n_j(const Args &a) { return a.n; }
+    static __device__ __forceinline__ Ctx make_ctx(const Args &a, int i0) {
+        const double *c = a.centres + 3 * (size_t)(i0 / a.itile);
+        return {c[0], c[1], c[2]};
+    }
+    static __device__ __forceinline__ IState load_i(const Args &a, const Ctx &c, int i) {
+        return {(float)(a.x[i] - c.cx), (float)(a.y[i] - c.cy), (float)(a.z[i] - c.cz), a.m[i],
+                (float)a.gx[i], (float)a.gy[i], (float)a.gz[i], a.gp ? (float)a.gp[i] : 0.0f};
+    }
+    static __device__ __forceinline__ void load_j(const Args &a, const Ctx &c, int j, float (&r)[8]) {
+        r[0] = (float)(a.x[j] - c.cx);
+        r[1] = (float)(a.y[j] - c.cy);
+        r[2] = (float)(a.z[j] - c.cz);
+        r[3] = a.m[j];
+        r[4] = (float)a.gx[j];
+        r[5] = (float)a.gy[j];
+        r[6] = (float)a.gz[j];
+        r[7] = a.gp ? (float)a.gp[j] : 0.0f;
+    }
+    static __device__ __forceinline__ void pad_j(float (&r)[8]) { Adjoint::pad_j(r); }
+    template <bool MASS>
+    static __device__ __forceinline__ void pair(const float *j, const IState &k, float eps2,
+                                                float (&acc)[4]) {
+        Adjoint::pair<MASS>(j, k, eps2, acc);
+    }
+};
+
+}  // namespace
+}  // namespace nbody
