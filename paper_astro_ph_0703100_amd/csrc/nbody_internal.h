@@ -345,7 +345,7 @@ nbody_status launch_system_centres(int nsys, const int64_t *offsets, int64_t tot
                                    const double *pos64, double *centre, hipStream_t s);
 nbody_status launch_batched_convert(int64_t total, const double *pos64, const int32_t *sys_of,
                                     const double *centre, float *pos32, hipStream_t s);
-// Force-jerk-potential kernel and its FP64 finalize (jerk.hip).
+// Force-jerk-potential kernels and their FP64 finalize (jerk.hip, jerk_tile.hip, jerk_ij.hip).
 nbody_status launch_jerk(const TileCfg &cfg, int precision, bool with_pot, const JerkArgs &a,
                          hipStream_t s);
 nbody_status launch_jerk_finalize(int precision, const JerkFinalizeArgs &a, hipStream_t s);
@@ -359,7 +359,7 @@ nbody_status launch_hermite_predict(int64_t n, const double *x, const double *v,
                                     hipStream_t s);
 nbody_status launch_hermite_correct(int64_t n, double *x, double *v, double *a, double *j,
                                     const double *a1, const double *j1, double dt, hipStream_t s);
-// Adjoint pair kernel and its FP64 finalize (vjp.hip).
+// Adjoint pair kernels and their FP64 finalize (vjp.hip, vjp_tile.hip).
 nbody_status launch_vjp(const TileCfg &cfg, int precision, const VjpArgs &a, bool with_mass,
                         hipStream_t s);
 nbody_status launch_vjp_tile(const TileCfg &cfg, int precision, const VjpTileArgs &a,
