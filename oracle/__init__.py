@@ -13,6 +13,9 @@ Parity status of each function (what pins it; the pins are in tests/test_oracle.
   force_ij with eps_i : two-body closed forms with a different softening per
       i-particle (including eps = 0), 50-digit brute force on separate i- and
       j-sets with per-i softening.
+  force_abs           : equals |a_c| and |phi| (from the pinned force functions) for
+      positive masses lying on one side of every i along each axis; otherwise it
+      bounds them; it is the same pair set as force_ij / force_sampled.
   force_jerk          : two-body closed form, central time differences of
       force_all along x + v t, 50-digit brute force, sum_i m_i jerk_i = 0,
       exact power-of-two scaling of v, Galilean invariance.
@@ -23,7 +26,10 @@ Parity status of each function (what pins it; the pins are in tests/test_oracle.
       invariance, degree-1 homogeneity in the masses.
   rollout             : time reversibility, second-order energy error, two-body
       circular orbit.
-  rollout_loss_grad   : central finite differences of the rollout loss.
+  rollout_loss_grad   : central finite differences of the rollout loss (n = 12, and
+      at the full N = 16384, 32-step differentiation workload in a slow test).
+  rollout_vjp         : central finite differences of a loss on both final positions
+      and final velocities, zero steps (identity) and one step included.
   hermite             : two-body circular orbit with fourth-order phase error,
       fourth-order energy error, agreement with the (pinned) leapfrog at a much
       smaller step, exact free motion.
@@ -72,6 +78,8 @@ def _load():
                                            _I64, _D, _D]
             lib.oracle_set_threads.argtypes = [ctypes.c_int]
             lib.oracle_force_epsi.argtypes = [_I64, _D, _D, _I64, _D, _D, _D, _D]
+            lib.oracle_force_abs.argtypes = [_I64, _D, _D, _I64, _D, _L, ctypes.c_double, _D, _D]
+            lib.oracle_force_abs.restype = None
             lib.oracle_force_jerk.argtypes = [_I64, _D, _D, _D, _I64, _D, _D, _L, ctypes.c_double,
                                               _D, _D, _D]
             lib.oracle_force_all.argtypes = [_I64, _D, _D, ctypes.c_double, _D, _D]
@@ -82,6 +90,9 @@ def _load():
             lib.oracle_rollout_loss_grad.argtypes = [_I64, _D, _D, _D, ctypes.c_double,
                                                      ctypes.c_double, _I64, _D, _D, _D, _D]
             lib.oracle_rollout_loss_grad.restype = ctypes.c_double
+            lib.oracle_rollout_vjp.argtypes = [_I64, _D, _D, _D, ctypes.c_double, ctypes.c_double,
+                                               _I64, _D, _D, _D, _D, _D]
+            lib.oracle_rollout_vjp.restype = None
             lib.oracle_fp32_replay.argtypes = [_I64, _F, _F, ctypes.c_float, _I64, _I64, _L, _D]
             lib.oracle_threads.restype = ctypes.c_int
             for f in (lib.oracle_force, lib.oracle_force_all, lib.oracle_force_sampled,
@@ -165,6 +176,28 @@ def force_ij(xj, mj, xi, eps, self_index=None, eps_i=None):
     pot = np.empty(ni)
     _load().oracle_force(nj, _p(xj), _p(mj), ni, _p(xi), _p(si, _L), float(eps), _p(acc), _p(pot))
     return acc, pot
+
+
+def force_abs(xj, mj, xi, eps, self_index=None):
+    """Magnitude sums for rounding bounds on the i-particles ``xi`` from the j-set:
+    (sum_j |m_j d_c| / s^3 per component (ni, 3), sum_j |m_j| / s (ni,)), skipping
+    j = ``self_index[i]`` (None: no pair skipped)."""
+    xj = _f64(xj)
+    xi = _f64(xi)
+    nj, ni = xj.shape[0], xi.shape[0]
+    mj = _f64(mj, (nj,))
+    si = None if self_index is None else np.ascontiguousarray(self_index, dtype=np.int64)
+    absa, absp = np.empty((ni, 3)), np.empty(ni)
+    _load().oracle_force_abs(nj, _p(xj), _p(mj), ni, _p(xi), _p(si, _L), float(eps), _p(absa),
+                             _p(absp))
+    return absa, absp
+
+
+def force_abs_sampled(x, m, eps, idx):
+    """force_abs of the particles ``idx`` of one set from all of it, self pair skipped."""
+    x = _f64(x)
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    return force_abs(x, m, x[idx], eps, self_index=idx)
 
 
 def force_jerk(x, v, m, eps, idx=None):
@@ -255,6 +288,21 @@ def rollout_loss_grad(x0, v0, m, eps, dt, nsteps, target):
     loss = _load().oracle_rollout_loss_grad(n, _p(x0), _p(v0), _p(m), float(eps), float(dt),
                                             int(nsteps), _p(y), _p(gx), _p(gv), _p(gm))
     return float(loss), gx, gv, gm
+
+
+def rollout_vjp(x0, v0, m, eps, dt, nsteps, xbar_T=None, vbar_T=None):
+    """(dL/dx0, dL/dv0, dL/dm) of ``nsteps`` KDK steps for the cotangents ``xbar_T`` =
+    dL/dx_T and ``vbar_T`` = dL/dv_T of the final state (``(n, 3)``; None = zero)."""
+    x0 = _f64(x0)
+    n = x0.shape[0]
+    v0 = _f64(v0, (n, 3))
+    m = _f64(m, (n,))
+    xb = None if xbar_T is None else _f64(xbar_T, (n, 3))
+    vb = None if vbar_T is None else _f64(vbar_T, (n, 3))
+    gx, gv, gm = np.empty((n, 3)), np.empty((n, 3)), np.empty(n)
+    _load().oracle_rollout_vjp(n, _p(x0), _p(v0), _p(m), float(eps), float(dt), int(nsteps),
+                               _p(xb), _p(vb), _p(gx), _p(gv), _p(gm))
+    return gx, gv, gm
 
 
 def fp32_replay(x32, m32, eps2_32, nbag, idx):

@@ -96,6 +96,42 @@ OR_EXPORT void oracle_force_epsi(int64_t nj, const double *xj, const double *mj,
     }
 }
 
+/* Magnitude sums of the terms of eq. (1) and of the potential, for rounding-error   */
+/* bounds: absa[3 i + c] = sum_j |m_j d_c| / s^3 and absp[i] = sum_j |m_j| / s, over  */
+/* the same pairs as oracle_force (self[i] skipped; self may be NULL).  With         */
+/* positive masses and every d_c of one sign, absa is |a_c|; absp is |phi| always.   */
+OR_EXPORT void oracle_force_abs(int64_t nj, const double *xj, const double *mj,
+                                int64_t ni, const double *xi, const int64_t *self,
+                                double eps, double *absa, double *absp)
+{
+    const double eps2 = eps * eps;
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int64_t i = 0; i < ni; ++i) {
+        const int64_t skip = self ? self[i] : -1;
+        double ax = 0.0, ay = 0.0, az = 0.0, ph = 0.0;
+        for (int64_t j = 0; j < nj; ++j) {
+            if (j == skip)
+                continue;
+            const double dx = xj[3 * j + 0] - xi[3 * i + 0];
+            const double dy = xj[3 * j + 1] - xi[3 * i + 1];
+            const double dz = xj[3 * j + 2] - xi[3 * i + 2];
+            const double s2 = dx * dx + dy * dy + dz * dz + eps2;
+            const double s = sqrt(s2);
+            const double s3 = s2 * s;
+            const double mm = fabs(mj[j]);
+            ax += mm * fabs(dx) / s3;
+            ay += mm * fabs(dy) / s3;
+            az += mm * fabs(dz) / s3;
+            ph += mm / s;
+        }
+        absa[3 * i + 0] = ax;
+        absa[3 * i + 1] = ay;
+        absa[3 * i + 2] = az;
+        if (absp)
+            absp[i] = ph;
+    }
+}
+
 /* All-pairs convenience: i-set == j-set, self pair excluded. */
 OR_EXPORT void oracle_force_all(int64_t n, const double *x, const double *m,
                                 double eps, double *acc, double *pot)
@@ -250,9 +286,10 @@ OR_EXPORT void oracle_rollout(int64_t n, double *x, double *v, const double *m, 
 }
 
 /* ------------------------------------------------------------------------- */
-/* Loss L = (1/n) sum_i |x_i(T) - y_i|^2 after nsteps KDK steps from (x0, v0), */
-/* and its gradient with respect to x0, v0 and m by reverse mode through the  */
-/* KDK map.  Reverse of one step (x_t, v_t) -> (x_{t+1}, v_{t+1}), h = dt/2:  */
+/* Reverse mode through nsteps KDK steps whose positions x_0 .. x_nsteps are  */
+/* stored in traj.  On entry xb, vb hold dL/dx_T, dL/dv_T; on exit dL/dx_0,   */
+/* dL/dv_0; dL/dm is added to mb.  Reverse of one step (x_t, v_t) ->          */
+/* (x_{t+1}, v_{t+1}), h = dt/2:                                              */
 /*   abar_{t+1} += h vbar_{t+1}          (second kick used a(x_{t+1}))         */
 /*   xbar_{t+1} += VJP_x(x_{t+1}, abar_{t+1}); mbar += VJP_m(...)             */
 /*   vbar_half   = vbar_{t+1} + dt xbar_{t+1}                                 */
@@ -260,6 +297,43 @@ OR_EXPORT void oracle_rollout(int64_t n, double *x, double *v, const double *m, 
 /*   abar_t      = h vbar_half           (first kick used a(x_t))             */
 /* and finally xbar_0 += VJP_x(x_0, abar_0).  The two kicks that use a(x_t)   */
 /* have their cotangents summed before one VJP, as a(x_t) is one evaluation.  */
+/* With nsteps = 0 abar_0 = 0: the map is the identity.                       */
+/* ------------------------------------------------------------------------- */
+static void reverse_kdk(int64_t n, const double *traj, const double *m, double eps, double dt,
+                        int64_t nsteps, double *xb, double *vb, double *mb)
+{
+    const size_t n3 = 3 * (size_t)n;
+    const size_t nn = n3 ? n3 : 1;
+    double *ab = (double *)calloc(nn, sizeof(double));
+    double *tx = (double *)malloc(sizeof(double) * nn);
+    double *tm = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    const double h = 0.5 * dt;
+    for (int64_t t = nsteps - 1; t >= 0; --t) {
+        const double *x1 = traj + (size_t)(t + 1) * n3;
+        for (size_t q = 0; q < n3; ++q)
+            ab[q] += h * vb[q];
+        oracle_vjp(n, x1, m, eps, ab, NULL, tx, tm);
+        for (size_t q = 0; q < n3; ++q)
+            xb[q] += tx[q];
+        for (int64_t i = 0; i < n; ++i)
+            mb[i] += tm[i];
+        for (size_t q = 0; q < n3; ++q) {
+            vb[q] += dt * xb[q];
+            ab[q] = h * vb[q];
+        }
+    }
+    oracle_vjp(n, traj, m, eps, ab, NULL, tx, tm);
+    for (size_t q = 0; q < n3; ++q)
+        xb[q] += tx[q];
+    for (int64_t i = 0; i < n; ++i)
+        mb[i] += tm[i];
+    free(ab); free(tx); free(tm);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Loss L = (1/n) sum_i |x_i(T) - y_i|^2 after nsteps KDK steps from (x0, v0), */
+/* and its gradient with respect to x0, v0 and m by reverse mode through the  */
+/* KDK map (reverse_kdk with dL/dx_T = 2 (x_T - y) / n, dL/dv_T = 0).         */
 /* gx0, gv0, gm may each be NULL.  Returns L.                                 */
 /* ------------------------------------------------------------------------- */
 OR_EXPORT double oracle_rollout_loss_grad(int64_t n, const double *x0, const double *v0,
@@ -284,32 +358,10 @@ OR_EXPORT double oracle_rollout_loss_grad(int64_t n, const double *x0, const dou
 
     double *xb = (double *)calloc(nn, sizeof(double));
     double *vb = (double *)calloc(nn, sizeof(double));
-    double *ab = (double *)calloc(nn, sizeof(double));
-    double *tx = (double *)malloc(sizeof(double) * nn);
-    double *tm = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
     double *mb = (double *)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
     for (size_t q = 0; q < n3; ++q)
         xb[q] = 2.0 * (xT[q] - y[q]) / (double)n;
-    const double h = 0.5 * dt;
-    for (int64_t t = nsteps - 1; t >= 0; --t) {
-        const double *x1 = traj + (size_t)(t + 1) * n3;
-        for (size_t q = 0; q < n3; ++q)
-            ab[q] += h * vb[q];
-        oracle_vjp(n, x1, m, eps, ab, NULL, tx, tm);
-        for (size_t q = 0; q < n3; ++q)
-            xb[q] += tx[q];
-        for (int64_t i = 0; i < n; ++i)
-            mb[i] += tm[i];
-        for (size_t q = 0; q < n3; ++q) {
-            vb[q] += dt * xb[q];
-            ab[q] = h * vb[q];
-        }
-    }
-    oracle_vjp(n, traj, m, eps, ab, NULL, tx, tm);
-    for (size_t q = 0; q < n3; ++q)
-        xb[q] += tx[q];
-    for (int64_t i = 0; i < n; ++i)
-        mb[i] += tm[i];
+    reverse_kdk(n, traj, m, eps, dt, nsteps, xb, vb, mb);
 
     if (gx0)
         memcpy(gx0, xb, n3 * sizeof(double));
@@ -317,8 +369,42 @@ OR_EXPORT double oracle_rollout_loss_grad(int64_t n, const double *x0, const dou
         memcpy(gv0, vb, n3 * sizeof(double));
     if (gm)
         memcpy(gm, mb, (size_t)n * sizeof(double));
-    free(traj); free(x); free(v); free(xb); free(vb); free(ab); free(tx); free(tm); free(mb);
+    free(traj); free(x); free(v); free(xb); free(vb); free(mb);
     return loss;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Vector-Jacobian product of the whole rollout for any cotangents of the     */
+/* final state: given xbT = dL/dx_T and vbT = dL/dv_T (either NULL for zero),  */
+/* writes dL/dx0, dL/dv0 and dL/dm (each may be NULL).                        */
+/* ------------------------------------------------------------------------- */
+OR_EXPORT void oracle_rollout_vjp(int64_t n, const double *x0, const double *v0, const double *m,
+                                  double eps, double dt, int64_t nsteps, const double *xbT,
+                                  const double *vbT, double *gx0, double *gv0, double *gm)
+{
+    const size_t n3 = 3 * (size_t)n;
+    const size_t nn = n3 ? n3 : 1;
+    double *traj = (double *)malloc(sizeof(double) * nn * (size_t)(nsteps + 1));
+    double *x = (double *)malloc(sizeof(double) * nn);
+    double *v = (double *)malloc(sizeof(double) * nn);
+    memcpy(x, x0, n3 * sizeof(double));
+    memcpy(v, v0, n3 * sizeof(double));
+    oracle_rollout(n, x, v, m, eps, dt, nsteps, traj, NULL);
+    double *xb = (double *)calloc(nn, sizeof(double));
+    double *vb = (double *)calloc(nn, sizeof(double));
+    double *mb = (double *)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+    if (xbT)
+        memcpy(xb, xbT, n3 * sizeof(double));
+    if (vbT)
+        memcpy(vb, vbT, n3 * sizeof(double));
+    reverse_kdk(n, traj, m, eps, dt, nsteps, xb, vb, mb);
+    if (gx0)
+        memcpy(gx0, xb, n3 * sizeof(double));
+    if (gv0)
+        memcpy(gv0, vb, n3 * sizeof(double));
+    if (gm)
+        memcpy(gm, mb, (size_t)n * sizeof(double));
+    free(traj); free(x); free(v); free(xb); free(vb); free(mb);
 }
 
 /* ------------------------------------------------------------------------- */

@@ -526,3 +526,78 @@ def test_rollout_gradient_against_central_differences():
         mm[k] -= hm
         fd = (L(x0, v0, mp) - L(x0, v0, mm)) / (2 * hm)
         assert abs(fd - gm[k]) < 1e-6 * np.abs(gm).max(), (k, fd, gm[k])
+
+
+@pytest.mark.parametrize("steps", [0, 1, 5])
+def test_rollout_vjp_with_velocity_cotangent_against_central_differences(steps):
+    # L = sum G . x_T + sum H . v_T: both final positions and final velocities carry a
+    # cotangent.  Zero steps is the identity map (gradients G, H, 0); one step exercises
+    # the two kicks of a single step.
+    n, dt, eps = 10, 1.0 / 32, 0.1
+    x0, v0, m = ics.plummer(n, seed=61)
+    m = m * np.random.default_rng(62).uniform(0.5, 1.5, n)
+    rng = np.random.default_rng(63)
+    G, H = rng.standard_normal((n, 3)), rng.standard_normal((n, 3))
+    gx, gv, gm = oracle.rollout_vjp(x0, v0, m, eps, dt, steps, G, H)
+
+    def L(x, v, mm):
+        xT, vT, _, _ = oracle.rollout(x, v, mm, eps, dt, steps)
+        return float(np.sum(G * xT) + np.sum(H * vT))
+
+    if steps == 0:
+        assert np.array_equal(gx, G) and np.array_equal(gv, H) and not gm.any()
+    # A difference quotient carries the loss's rounding, a few u times the sum of the
+    # magnitudes of its terms, divided by the step.
+    xT, vT, _, _ = oracle.rollout(x0, v0, m, eps, dt, steps)
+    mag = float(np.sum(np.abs(G * xT)) + np.sum(np.abs(H * vT)))
+    noise = lambda step: 16 * 2.0 ** -53 * mag / step
+    h = 1e-6
+    for k in range(n):
+        for c in range(3):
+            xp, xm = x0.copy(), x0.copy()
+            xp[k, c] += h
+            xm[k, c] -= h
+            fd = (L(xp, v0, m) - L(xm, v0, m)) / (2 * h)
+            assert abs(fd - gx[k, c]) < 1e-7 * np.abs(gx).max() + noise(h), (k, c, fd, gx[k, c])
+            vp, vm = v0.copy(), v0.copy()
+            vp[k, c] += h
+            vm[k, c] -= h
+            fd = (L(x0, vp, m) - L(x0, vm, m)) / (2 * h)
+            assert abs(fd - gv[k, c]) < 1e-7 * np.abs(gv).max() + noise(h), (k, c, fd, gv[k, c])
+        hm = 1e-6 * m[k]
+        mp, mm = m.copy(), m.copy()
+        mp[k] += hm
+        mm[k] -= hm
+        fd = (L(x0, v0, mp) - L(x0, v0, mm)) / (2 * hm)
+        assert abs(fd - gm[k]) < 1e-7 * np.abs(gm).max() + noise(hm), (k, fd, gm[k])
+
+
+def test_rollout_vjp_matches_the_loss_gradient():
+    n, steps, dt, eps = 16, 4, 1.0 / 64, 0.1
+    x0, v0, m = ics.plummer(n, seed=64)
+    y = ics.perturbed_target(x0, seed=65, scale=0.05)
+    loss, gx, gv, gm = oracle.rollout_loss_grad(x0, v0, m, eps, dt, steps, y)
+    xT, _, _, _ = oracle.rollout(x0, v0, m, eps, dt, steps)
+    rx, rv, rm = oracle.rollout_vjp(x0, v0, m, eps, dt, steps, 2.0 * (xT - y) / n, None)
+    assert np.array_equal(rx, gx) and np.array_equal(rv, gv) and np.array_equal(rm, gm)
+
+
+def test_force_abs_sums_pin():
+    # j-particles all above-right-front of every i-particle (each separation component
+    # positive) with positive masses: no term cancels, so the magnitude sums equal the
+    # pinned force and potential; on a Plummer sphere they bound them, over the same
+    # pairs as force_sampled.
+    rng = np.random.default_rng(71)
+    xi = rng.uniform(-1.0, 0.0, (20, 3))
+    xj = rng.uniform(0.5, 2.0, (50, 3))
+    mj = rng.uniform(0.1, 1.0, 50)
+    absa, absp = oracle.force_abs(xj, mj, xi, 0.05)
+    a, p = oracle.force_ij(xj, mj, xi, 0.05)
+    np.testing.assert_allclose(absa, np.abs(a), rtol=1e-14)
+    np.testing.assert_allclose(absp, np.abs(p), rtol=1e-14)
+    x, _, m = ics.plummer(300, seed=72, velocities=False)
+    idx = np.arange(0, 300, 7)
+    absa, absp = oracle.force_abs_sampled(x, m, 0.02, idx)
+    a, p = oracle.force_sampled(x, m, 0.02, idx)
+    assert np.all(absa >= np.abs(a) * (1 - 1e-14)) and np.all(absa > 0)
+    np.testing.assert_allclose(absp, np.abs(p), rtol=1e-13)
