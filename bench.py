@@ -11,30 +11,33 @@ with the second kick.  ``value`` is N^2 * steps / wall time (pair interactions p
 second, inputs resident in HBM).  The same is timed with plain FP32 accumulation and
 with FP64-reduced accumulation ("modes").
 
-Other workloads (same JSON shape; ``value`` always counts the pair interactions the
-step evaluates):
-  stress_1m      2^20-particle precision-stress system at (1000,0,0), Morton-ordered,
-                 per-i-tile FP64 centres; step = one force+potential evaluation.
-  clusters_2048  2048 ragged Plummer clusters; step = one graph-replayed batched KDK
-                 step (persistent work-queue kernel); pairs = sum N_k^2.
-  adjoint_16384  N = 16384, 32 KDK steps dt = 1/256 and the reverse pass; step = one
-                 loss + gradient (33 force and 33 adjoint evaluations of N^2 pairs).
-  shard8_131072  one GPU's share of an 8-way i-split of the N = 131072 sphere: force and
-                 potential on 16384 i-particles from all 131072 (separate i- and j-sets);
-                 step = one evaluation.
-  active8_131072 a seeded eighth (16384) of the N = 131072 sphere as the active set of a
-                 Hermite code with individual steps: step = one force+jerk+potential
-                 evaluation of those particles from all 131072 (separate i- and j-sets).
-  jerk_131072    the N = 131072 sphere; step = one graph-replayed fourth-order Hermite
-                 step (dt = 1/256): FP64 predictor, one N^2 force+jerk evaluation from
-                 the predicted state, FP64 corrector.
+The default run also measures the other configurations of the workload set and puts
+one compact entry per configuration into ``configs`` (same units; each with its own
+accuracy against the FP64 oracle on the configuration's stated sample):
+  plummer_2048   N = 2048 sphere, v = 0, eps = 1/64: one force+potential evaluation,
+                 every mode, oracle on all N^2 pairs.
+  stress_1m      2^20-particle precision-stress system at (1000,0,0), Morton-ordered:
+                 one evaluation from FP64 positions, modes x reference centres (none,
+                 system, tile), oracle on 4096 stratified particles, and the same
+                 oracle on the FP32-rounded inputs the kernel saw (representation
+                 error apart from arithmetic error).
+  clusters_2048  2048 ragged Plummer clusters: one graph-replayed batched KDK step
+                 (persistent work-queue kernel); pairs = sum N_k^2; 16 systems checked
+                 (acceleration and potential) at step 0 and after the timed steps.
+  adjoint_16384  N = 16384, 32 KDK steps dt = 1/256 and the reverse pass: one loss +
+                 gradient (33 force and 33 adjoint evaluations of N^2 pairs).
+``--no-configs`` leaves them out; ``--workload`` runs one of them (or the secondary
+workloads shard8_131072, active8_131072, jerk_131072) as the whole line.
 
 Roofline: the dominant kernel's duration is taken from HIP events on the launch
-stream (standalone calls), and compared with the VALU issue limit: 17 slots per
-gravity pair (13 FP32 operations and a quarter-rate v_rsq_f32), 31 per
-force-jerk-potential pair, 42 per adjoint pair, at 256 CUs x 4 SIMDs x 32 lanes x
-2.4 GHz.  ``traffic`` comes from the committed rocprofv3 counter summary of the
-same kernel and is null when the kernel sources changed since it was taken.
+stream (standalone calls) and its algorithmic work (20 flop per gravity pair, the
+paper's count; 60 per force-jerk-potential pair; 45 per adjoint pair) is compared
+with the published FP32 vector peak of the MI355X, 157.3 TFLOP/s (``frac``).  Beside
+it, ``issue_model`` compares the pair rate with the VALU issue limit of the pair body:
+13 FP32 VALU instructions at 32 lanes per clock and one quarter-rate v_rsq_f32 (17
+issue slots per gravity pair; 31 per force-jerk-potential pair, 42 per adjoint pair)
+at 256 CUs x 4 SIMDs x 2.4 GHz.  ``traffic`` comes from the committed rocprofv3
+counter summary of the same kernel and is null when its sources changed since.
 
 Accuracy: the CPU-baseline leg runs the FP64 oracle on a bounded sample of the same
 workload; its result gives the relative RMS and maximum (eq. (3)) errors of each
@@ -64,32 +67,36 @@ if ROOT not in sys.path:
 
 METRIC = "pair interactions/s at N=131072, compensated vs plain FP32, error vs FP64"
 
-# MI355X issue model: 256 CUs x 4 SIMDs, each issuing FP32 VALU work for 32 lanes per
-# clock (a wave64 FP32 add/mul/FMA every 2 clocks, which is the 157.3 TFLOP/s FP32
-# figure with FMA = 2 flops) at 2.4 GHz: 7.86e13 lane-operations per second.  A
-# transcendental (v_rsq_f32) issues at a quarter of that rate, so it takes 4 slots.
+# Published FP32 vector peak of the MI355X (FMA = 2 flops), the roofline's peak.
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+# Issue model of the pair bodies: 256 CUs x 4 SIMDs, FP32 VALU work for 32 lanes per
+# clock (a wave64 instruction every 2 clocks; 157.3 TFLOP/s is that rate with FMA = 2
+# flops) at 2.4 GHz; a transcendental (v_rsq_f32) issues at a quarter of that rate and
+# takes 4 slots.  The pair kernel's own counters bear the model out (its committed
+# summary: 0.35 VALU wave-instructions per SIMD per cycle, above the 0.25 a 4-clock
+# wave64 issue allows).
 CUS, SIMDS, LANES, CLOCK_HZ = 256, 4, 32, 2.4e9
 LANE_ISSUE = CUS * SIMDS * LANES * CLOCK_HZ
-FP32_VECTOR_PEAK_TFLOPS = 157.3  # the published FP32 vector figure (FMA = 2 flops)
 RSQ_SLOTS = 4
 SLOTS = {"gravity": 13 + RSQ_SLOTS, "jerk": 27 + RSQ_SLOTS, "adjoint": 38 + RSQ_SLOTS}
 # Flops per pair: the paper's count for gravity (Sec. 1.1); 60 for force, jerk and
 # potential, the count customary for fourth-order Hermite codes; 45 for the adjoint.
 FLOPS = {"gravity": 20, "jerk": 60, "adjoint": 45}
 
-# Kernel sources behind the committed counter summaries, and the tuning file whose
-# force-kernel entries for N = 131072 (size bucket 17) pick the launch shape (traffic is
-# dropped when either changes).
 # The files that define the pair kernel tile_kernel<Gravity> (force.hip only instantiates
-# it; its own kernels are the finalize and centre passes).
+# it; its own kernels are the finalize and centre passes), and the tuning file whose
+# force-kernel entries for N = 131072 (size bucket 17) pick the launch shape; the
+# committed counter record is dropped when either changes.
 KERNEL_SOURCES = ["paper_astro_ph_0703100_amd/csrc/nbody_internal.h",
                   "paper_astro_ph_0703100_amd/csrc/tile_engine.h",
                   "paper_astro_ph_0703100_amd/csrc/gravity.h"]
 TUNING_FILE = "paper_astro_ph_0703100_amd/tuning_gfx950.json"
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "pair_kernel_plummer_131072.md")
+CONFIG_WORKLOADS = ("plummer_2048", "stress_1m", "clusters_2048", "adjoint_16384")
 
 
 def peak_pairs(kind: str) -> float:
+    """Pair rate of the issue model for a pipeline (pairs/s at the 2.4 GHz spec clock)."""
     return LANE_ISSUE / SLOTS[kind]
 
 
@@ -136,7 +143,18 @@ def committed_traffic():
     return rec["bytes_per_launch"] if rec else None
 
 
-def parse():
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def parse(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=8)
@@ -147,6 +165,8 @@ def parse():
                     choices=["plummer_131072", "plummer_2048", "stress_1m", "clusters_2048",
                              "adjoint_16384", "jerk_131072", "shard8_131072",
                              "active8_131072"])
+    ap.add_argument("--no-configs", action="store_true",
+                    help="measure only the selected workload (no per-configuration entries)")
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the FP64 oracle leg (no errors, no CPU rate)")
     ap.add_argument("--cpu-sample", type=int, default=0,
@@ -156,7 +176,7 @@ def parse():
                     help="first run one device-to-device copy of this many MiB from a source "
                          "evicted from the caches (a plain copy kernel of known size, to "
                          "calibrate hardware byte counters)")
-    return ap.parse_args()
+    return ap.parse_args(argv)
 
 
 class Timer:
@@ -225,6 +245,12 @@ def one_thread(cpu, call, pairs, what):
     cpu["sample_1_thread"] = "%s (%.2f s)" % (what, ct)
 
 
+def cpu_entry(value, sample):
+    import oracle
+    return {"value": value, "unit": "pair-interactions/s", "cores": oracle.threads(),
+            "cpu_model": cpu_model(), "kind": "oracle", "sample": sample}
+
+
 def errors_of(metrics, acc, pot, ra, rp):
     ea = metrics.rel_errors(acc, ra)
     out = {"acc_rel_rms": ea["rel_rms"], "acc_e_max": ea["e_max"], "acc_normwise": ea["normwise"],
@@ -236,21 +262,38 @@ def errors_of(metrics, acc, pot, ra, rp):
 
 
 def roofline(kind, pairs_per_launch, kernel_ms, kernel_name, traffic=None):
-    achieved = pairs_per_launch * FLOPS[kind] / (kernel_ms * 1e-3) / 1e12
-    peak = peak_pairs(kind) * FLOPS[kind] / 1e12
-    return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-            "frac": achieved / peak, "traffic": traffic, "kernel": kernel_name,
-            "fp32_vector_peak_frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
-            "kernel_ms": kernel_ms, "flops_per_pair": FLOPS[kind],
-            "issue_slots_per_pair": SLOTS[kind], "peak_pairs_per_s": peak_pairs(kind)}
+    """Roofline of one kernel: algorithmic TFLOP/s against the published FP32 vector peak
+    (``frac``), and the pair rate against the issue model (``issue_model``)."""
+    pairs_s = pairs_per_launch / (kernel_ms * 1e-3)
+    achieved = pairs_s * FLOPS[kind] / 1e12
+    return {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": traffic,
+            "kernel": kernel_name, "kernel_ms": kernel_ms, "flops_per_pair": FLOPS[kind],
+            "pairs_per_s": pairs_s,
+            "issue_model": {"peak_pairs_per_s": peak_pairs(kind),
+                            "peak_tflops": peak_pairs(kind) * FLOPS[kind] / 1e12,
+                            "issue_slots_per_pair": SLOTS[kind],
+                            "frac": pairs_s / peak_pairs(kind)}}
+
+
+def fractions(kind, pairs_per_launch, kernel_ms):
+    """Both roofline fractions of one kernel timing (compact form)."""
+    r = roofline(kind, pairs_per_launch, kernel_ms, "")
+    return {"kernel_ms": kernel_ms, "pairs_per_s": r["pairs_per_s"], "frac": r["frac"],
+            "issue_frac": r["issue_model"]["frac"]}
+
+
+def modes_of(args):
+    return [s for s in args.modes.split(",") if s]
 
 
 # --------------------------------------------------------------------------- workloads
 def bench_plummer(args, torch, w):
+    """The headline: graph-replayed KDK steps of the N = 131072 sphere, every mode."""
     from paper_astro_ph_0703100_amd import _lib, api, ics, metrics
     n = w.n
     dt = w.dt or 1.0 / 256
-    pos, vel, mass = ics.plummer(n, seed=w.seed, velocities=(w.name != "plummer_2048"))
+    pos, vel, mass = ics.plummer(n, seed=w.seed)
     m32 = mass.astype(np.float32)
     eps = float(np.float32(w.eps))
     dev = torch.device("cuda:0")
@@ -262,7 +305,7 @@ def bench_plummer(args, torch, w):
     timer = Timer(torch)
     pairs = float(n) * float(n)
     res = {}
-    for precision in [s for s in args.modes.split(",") if s]:
+    for precision in modes_of(args):
         x, v = x0.clone(), v0.clone()
         acc, _, _ = api.leapfrog(x, v, m, eps, dt, 0, precision=precision)
         pot = torch.empty(n, dtype=torch.float64, device=dev)
@@ -294,10 +337,9 @@ def bench_plummer(args, torch, w):
         t0 = time.perf_counter()
         ra, rp = oracle.force_sampled(pos, m32.astype(np.float64), eps, idx)
         ct = time.perf_counter() - t0
-        cpu = {"value": k * pairs / n / ct, "unit": "pair-interactions/s",
-               "cores": oracle.threads(), "kind": "oracle",
-               "sample": "force+potential of %d i-particles from all %d particles of the same "
-                         "sphere at the initial positions, FP64 (%.1f s)" % (k, n, ct)}
+        cpu = cpu_entry(k * pairs / n / ct,
+                        "force+potential of %d i-particles from all %d particles of the same "
+                        "sphere at the initial positions, FP64 (%.1f s)" % (k, n, ct))
         i1 = ics.sample_indices(n, 512, seed=w.seed + 2000)
         one_thread(cpu, lambda: oracle.force_sampled(pos, m32.astype(np.float64), eps, i1),
                    512.0 * n, "force+potential of 512 sampled i-particles from all %d" % n)
@@ -305,13 +347,14 @@ def bench_plummer(args, torch, w):
             errors[p] = errors_of(metrics, r["acc"][idx], r["pot"][idx], ra, rp)
     head = next(iter(res))
     r0 = res[head]
-    rec = committed_record() if w.name == "plummer_131072" else None
+    rec = committed_record()
     roof = roofline("gravity", pairs, r0["kernel_ms"], "tile_kernel<Gravity> (+ finalize_kernel)",
                     rec["bytes_per_launch"] if rec else None)
     if rec and rec.get("sustained_clock_ghz"):
-        # The same roofline at the engine clock the counters measured under this load.
-        roof["sustained_clock_ghz"] = rec["sustained_clock_ghz"]
-        roof["frac_at_sustained_clock"] = roof["frac"] * CLOCK_HZ / (rec["sustained_clock_ghz"] * 1e9)
+        # The issue model at the engine clock the counters measured under this load.
+        roof["issue_model"]["sustained_clock_ghz"] = rec["sustained_clock_ghz"]
+        roof["issue_model"]["frac_at_sustained_clock"] = (
+            roof["issue_model"]["frac"] * CLOCK_HZ / (rec["sustained_clock_ghz"] * 1e9))
     return {
         "value": pairs * args.steps / r0["wall"], "ms_per_step": r0["wall"] / args.steps * 1e3,
         "config": {"workload": w.name, "n": n, "eps": eps, "seed": w.seed, "dt": dt,
@@ -325,7 +368,9 @@ def bench_plummer(args, torch, w):
                       "ms_per_step": r["wall"] / args.steps * 1e3,
                       "step_ms_events": float(np.mean(r["step_ms"])),
                       "force_kernel_ms": r["kernel_ms"],
-                      "roofline_frac": pairs / (r["kernel_ms"] * 1e-3) / peak_pairs("gravity"),
+                      **{"roofline_" + k: v for k, v in
+                         fractions("gravity", pairs, r["kernel_ms"]).items()
+                         if k in ("frac", "issue_frac")},
                       "errors": errors.get(p)} for p, r in res.items()},
         "gflops_38": pairs * 38 / (r0["kernel_ms"] * 1e-3) / 1e9,
         "gflops_20": pairs * 20 / (r0["kernel_ms"] * 1e-3) / 1e9,
@@ -333,13 +378,76 @@ def bench_plummer(args, torch, w):
         # including host transfers, eps^2 = 0.01, no potential): context only, another
         # machine and not the same workload, hence vs_baseline stays null.
         "paper_context": {"pairs_per_s": 131072.0 ** 2 / 2.548, "gflops_38": 256.0,
-                          "ratio": pairs * args.steps / r0["wall"] / (131072.0 ** 2 / 2.548)}
-        if n == 131072 else None,
+                          "ratio": pairs * args.steps / r0["wall"] / (131072.0 ** 2 / 2.548)},
     }
 
 
+def bench_small(args, torch, w):
+    """N = 2048 sphere: one force+potential evaluation per step (FP32 inputs), every mode,
+    against the oracle on all N^2 pairs."""
+    from paper_astro_ph_0703100_amd import _lib, api, ics, metrics
+    n = w.n
+    pos, _, mass = ics.plummer(n, seed=w.seed, velocities=False)
+    p32 = np.ascontiguousarray(pos.T.astype(np.float32))
+    m32 = mass.astype(np.float32)
+    eps = float(np.float32(w.eps))
+    dev = torch.device("cuda:0")
+    p, m = torch.from_numpy(p32).to(dev), torch.from_numpy(m32).to(dev)
+    acc = torch.empty((3, n), dtype=torch.float64, device=dev)
+    pot = torch.empty(n, dtype=torch.float64, device=dev)
+    sp = torch.cuda.current_stream().cuda_stream
+    timer = Timer(torch)
+    pairs = float(n) * n
+    reps = max(args.steps, 200)
+    res = {}
+    for precision in modes_of(args):
+        opts = api.make_opts(precision=precision)
+        call = lambda: _lib.nbody_force_ex(n, p.data_ptr(), m.data_ptr(), eps, acc.data_ptr(),
+                                           pot.data_ptr(), opts, sp)
+        wall, kms = timer.run(call, reps, warmup=args.warmup)
+        res[precision] = {"wall": wall, "kernel_ms": float(np.mean(kms)),
+                          "acc": acc.cpu().numpy().T.copy(), "pot": pot.cpu().numpy().copy()}
+        print("bench: %-8s N=%d  %.2f us per evaluation (events)" % (precision, n, np.mean(kms) * 1e3),
+              file=sys.stderr, flush=True)
+    cpu, errors = None, {}
+    if not args.no_cpu_baseline:
+        import oracle
+        x64, m64 = p32.T.astype(np.float64), m32.astype(np.float64)
+        t0 = time.perf_counter()
+        ra, rp = oracle.force_all(x64, m64, eps)
+        ct = time.perf_counter() - t0
+        cpu = cpu_entry(pairs / ct, "all %d^2 pairs, FP64 (%.2f s)" % (n, ct))
+        for q, r in res.items():
+            errors[q] = errors_of(metrics, r["acc"], r["pot"], ra, rp)
+    head = next(iter(res))
+    r0 = res[head]
+    return {
+        "value": pairs * reps / r0["wall"], "ms_per_step": r0["kernel_ms"],
+        "config": {"workload": w.name, "n": n, "eps": eps, "seed": w.seed, "precision": head,
+                   "step": "one force+potential evaluation (nbody_force_ex, FP32 inputs)",
+                   "description": w.description},
+        "roofline": roofline("gravity", pairs, r0["kernel_ms"], "force evaluation (all kernels)"),
+        "cpu_baseline": cpu,
+        "modes": {q: {"ms_per_step": r["kernel_ms"], **fractions("gravity", pairs, r["kernel_ms"]),
+                      "errors": errors.get(q)} for q, r in res.items()},
+    }
+
+
+def _tile_rounded_rows(pos, centres_of, idx, itile):
+    """The FP32-rounded relative positions the tile-centre kernel sees for i-particles
+    ``idx``: every particle converted relative to the centre of i's tile (the FP64 mean
+    of the tile, here summed by numpy: it may differ from the kernel's fixed-order sum
+    in the last bit, so this is the representation error to that accuracy)."""
+    out = {}
+    for t in np.unique(idx // itile):
+        c = centres_of(t)
+        out[int(t)] = (pos - c).astype(np.float32).astype(np.float64)
+    return out
+
+
 def bench_stress(args, torch, w):
-    from paper_astro_ph_0703100_amd import api, ics, metrics
+    """2^20 precision-stress system from FP64 positions: modes x reference centres."""
+    from paper_astro_ph_0703100_amd import _lib, api, ics, metrics
     n = w.n
     pos, mass, core = ics.stress_system(n, seed=w.seed)
     dev = torch.device("cuda:0")
@@ -352,42 +460,71 @@ def bench_stress(args, torch, w):
     m = torch.from_numpy(m32).to(dev)
     timer = Timer(torch)
     pairs = float(n) * float(n)
+    centres = ("tile", "system", "none")
     res = {}
-    for precision in [s for s in args.modes.split(",") if s]:
+    for precision in modes_of(args):
         out = {}
-        for centre in ("tile", "system"):
+        for centre in centres:
             acc = torch.empty((3, n), dtype=torch.float64, device=dev)
             pot = torch.empty(n, dtype=torch.float64, device=dev)
             call = lambda: api.force_f64(x, m, eps, precision=precision, centre=centre,
                                          out=(acc, pot))
-            wall, kms = timer.run(call, args.steps, warmup=args.warmup)
+            wall, kms = timer.run(call, max(2, min(args.steps, 3)), warmup=1)
             out[centre] = {"wall": wall, "kernel_ms": float(np.mean(kms)),
                            "acc": acc.cpu().numpy().T.copy(), "pot": pot.cpu().numpy().copy()}
         res[precision] = out
-        print("bench: %-8s tile %.3f ms  system %.3f ms" % (precision, out["tile"]["kernel_ms"],
-              out["system"]["kernel_ms"]), file=sys.stderr, flush=True)
-    cpu, errors = None, {}
+        print("bench: %-8s %s" % (precision, "  ".join("%s %.2f ms" % (c, out[c]["kernel_ms"])
+                                                      for c in centres)),
+              file=sys.stderr, flush=True)
+    cpu, errors, split = None, {}, {}
     if not args.no_cpu_baseline:
         import oracle
-        k = args.cpu_sample if args.cpu_sample > 0 else 8192
+        m64 = m32.astype(np.float64)
+        k = args.cpu_sample if args.cpu_sample > 0 else 2048
         idx = ics.stratified_indices(core, k, seed=w.seed + 1000)
         t0 = time.perf_counter()
-        ra, rp = oracle.force_sampled(pos, m32.astype(np.float64), eps, idx)
+        ra, rp = oracle.force_sampled(pos, m64, eps, idx)
         ct = time.perf_counter() - t0
-        cpu = {"value": idx.size * pairs / n / ct, "unit": "pair-interactions/s",
-               "cores": oracle.threads(), "kind": "oracle",
-               "sample": "%d stratified i-particles (half core, half halo) from all %d, FP64 "
-                         "(%.1f s)" % (idx.size, n, ct)}
-        one_thread(cpu, lambda: oracle.force_sampled(pos, m32.astype(np.float64), eps, idx[::16]),
+        cpu = cpu_entry(idx.size * pairs / n / ct,
+                        "%d stratified i-particles (half core, half halo) from all %d, FP64 "
+                        "(%.1f s)" % (idx.size, n, ct))
+        one_thread(cpu, lambda: oracle.force_sampled(pos, m64, eps, idx[::16]),
                    float(idx[::16].size) * n, "%d of those i-particles" % idx[::16].size)
         for p, out in res.items():
             for centre, r in out.items():
                 errors["%s/%s" % (p, centre)] = errors_of(metrics, r["acc"][idx], r["pot"][idx],
                                                           ra, rp)
+        # Representation error apart from arithmetic error: the oracle on the FP32-rounded
+        # relative positions each centre mode hands the pair kernel.  none: fp32(x);
+        # system: fp32(x - c), c the FP64 mean; tile: fp32(x - c_I) of each sampled i's
+        # tile (on 256 of the sampled particles, one conversion of all N per tile).
+        rounded = {"none": pos.astype(np.float32).astype(np.float64),
+                   "system": (pos - pos.mean(0)).astype(np.float32).astype(np.float64)}
+        for centre in ("none", "system"):
+            rx = rounded[centre]
+            ca, cp = oracle.force_sampled(rx, m64, eps, idx)
+            rep = errors_of(metrics, ca, cp, ra, rp)
+            split[centre] = {"representation": rep, "arithmetic": {
+                p: errors_of(metrics, res[p][centre]["acc"][idx], res[p][centre]["pot"][idx],
+                             ca, cp) for p in res}}
+        itile = 256 * _lib.nbody_tune_get(0, 2, n)[0]
+        sub = idx[:: max(1, idx.size // 256)]
+        ta, tp = np.empty((sub.size, 3)), np.empty(sub.size)
+        for t, rows in _tile_rounded_rows(pos, lambda t: pos[t * itile:(t + 1) * itile].mean(0),
+                                          sub, itile).items():
+            sel = np.nonzero(sub // itile == t)[0]
+            a_, p_ = oracle.force_sampled(rows, m64, eps, sub[sel])
+            ta[sel], tp[sel] = a_, p_
+        ra_sub, rp_sub = oracle.force_sampled(pos, m64, eps, sub)
+        split["tile"] = {"representation": errors_of(metrics, ta, tp, ra_sub, rp_sub),
+                         "arithmetic": {p: errors_of(metrics, res[p]["tile"]["acc"][sub],
+                                                     res[p]["tile"]["pot"][sub], ta, tp)
+                                        for p in res},
+                         "sample": int(sub.size)}
     head = next(iter(res))
     r0 = res[head]["tile"]
     return {
-        "value": pairs * args.steps / r0["wall"], "ms_per_step": r0["wall"] / args.steps * 1e3,
+        "value": pairs / (r0["kernel_ms"] * 1e-3), "ms_per_step": r0["kernel_ms"],
         "config": {"workload": w.name, "n": n, "eps": eps, "seed": w.seed, "precision": head,
                    "centre": "tile (Morton order)",
                    "step": "one force+potential evaluation from FP64 positions, FP32 pair "
@@ -396,41 +533,51 @@ def bench_stress(args, torch, w):
         "roofline": roofline("gravity", pairs, r0["kernel_ms"],
                              "tile_kernel<GravityTile> (+ centres, finalize)"),
         "cpu_baseline": cpu,
-        "modes": {"%s/%s" % (p, c): {"value": pairs * args.steps / r["wall"],
-                                     "kernel_ms": r["kernel_ms"],
+        "modes": {"%s/%s" % (p, c): {"ms_per_step": r["kernel_ms"],
+                                     **fractions("gravity", pairs, r["kernel_ms"]),
                                      "errors": errors.get("%s/%s" % (p, c))}
                   for p, out in res.items() for c, r in out.items()},
+        "error_split": split or None,
     }
 
 
 def bench_clusters(args, torch, w):
+    """2048 ragged clusters: graph-replayed batched KDK steps (persistent kernel)."""
     from paper_astro_ph_0703100_amd import api, ics, metrics
     b = ics.cluster_batch(w.n, seed=w.seed, eps=w.eps)
     dev = torch.device("cuda:0")
     m32 = b.mass.astype(np.float32)
+    epsk = b.eps.astype(np.float32)
     x0 = torch.from_numpy(np.ascontiguousarray(b.pos.T)).to(dev)
     v0 = torch.from_numpy(np.ascontiguousarray(b.vel.T)).to(dev)
     m = torch.from_numpy(m32).to(dev)
-    e = torch.from_numpy(b.eps.astype(np.float32)).to(dev)
+    e = torch.from_numpy(epsk).to(dev)
     p32 = torch.from_numpy(np.ascontiguousarray(b.pos.T.astype(np.float32))).to(dev)
     timer = Timer(torch)
     res = {}
     pairs = None
-    for precision in [s for s in args.modes.split(",") if s]:
+    for precision in modes_of(args):
         plan = api.BatchPlan(b.offsets, precision=precision)
         info = plan.info()
         pairs = float(info["pairs"])
         x, v = x0.clone(), v0.clone()
-        acc, _ = plan.leapfrog(x, v, m, e, w.dt, 0)
-        g = plan.graph(x, v, m, e, w.dt, 1, acc)
+        acc, pot0 = plan.leapfrog(x, v, m, e, w.dt, 0, with_pot=True)
+        a0 = acc.cpu().numpy().T.copy()
+        p0 = pot0.cpu().numpy().copy()
+        pot = torch.empty_like(pot0)
+        g = plan.graph(x, v, m, e, w.dt, 1, acc, pot)
         warm_up(torch, g.launch, args.warmup)
+        x.copy_(x0)
+        v.copy_(v0)
+        plan.leapfrog(x, v, m, e, w.dt, 0, acc=acc)
         wall, step_ms = timer.run(g.launch, args.steps, warmup=0)
         g.close()
-        _, kms = timer.run(lambda: plan.force(p32, m, e), max(args.steps, 3), warmup=args.warmup)
-        a, _ = plan.force_f64(x0, m, e)
         torch.cuda.synchronize()
-        res[precision] = {"wall": wall, "step_ms": step_ms, "kernel_ms": float(np.mean(kms)),
-                          "acc": a.cpu().numpy().T.copy(), "info": info}
+        res[precision] = {"wall": wall, "step_ms": step_ms, "info": info,
+                          "a0": a0, "p0": p0, "aT": acc.cpu().numpy().T.copy(),
+                          "pT": pot.cpu().numpy().copy(), "xT": x.cpu().numpy().T.copy()}
+        _, kms = timer.run(lambda: plan.force(p32, m, e), max(args.steps, 3), warmup=args.warmup)
+        res[precision]["kernel_ms"] = float(np.mean(kms))
         plan.close()
         print("bench: %-8s %d steps  %.3f ms/step  batched force %.3f ms  %s"
               % (precision, args.steps, wall / args.steps * 1e3, np.mean(kms), info),
@@ -441,24 +588,26 @@ def bench_clusters(args, torch, w):
         rng = np.random.default_rng(w.seed + 1000)
         pick = sorted(set([int(np.argmin(b.sizes)), int(np.argmax(b.sizes))] +
                           list(rng.choice(b.nsys, size=14, replace=False))))
-        t0 = time.perf_counter()
-        refs = {k: oracle.force_all(b.pos[b.offsets[k]:b.offsets[k + 1]],
+        sel = np.concatenate([np.arange(b.offsets[k], b.offsets[k + 1]) for k in pick])
+
+        def refs(pos):
+            out = [oracle.force_all(pos[b.offsets[k]:b.offsets[k + 1]],
                                     m32[b.offsets[k]:b.offsets[k + 1]].astype(np.float64),
-                                    float(np.float32(w.eps)))[0] for k in pick}
+                                    float(epsk[k])) for k in pick]
+            return np.concatenate([a for a, _ in out]), np.concatenate([p for _, p in out])
+
+        t0 = time.perf_counter()
+        ra0, rp0 = refs(b.pos)
         ct = time.perf_counter() - t0
         cpairs = float(sum(int(b.sizes[k]) ** 2 for k in pick))
-        cpu = {"value": cpairs / ct, "unit": "pair-interactions/s", "cores": oracle.threads(),
-               "kind": "oracle", "sample": "%d of the clusters (incl. smallest and largest), "
-                                           "%.3g pairs, FP64 (%.1f s)" % (len(pick), cpairs, ct)}
-        k1 = pick[0]
-        sl = slice(b.offsets[k1], b.offsets[k1 + 1])
-        one_thread(cpu, lambda: oracle.force_all(b.pos[sl], m32[sl].astype(np.float64),
-                                                 float(np.float32(w.eps))),
-                   float(b.sizes[k1]) ** 2, "cluster %d (N = %d)" % (k1, b.sizes[k1]))
+        cpu = cpu_entry(cpairs / ct, "%d of the clusters (incl. smallest and largest), %.3g "
+                                     "pairs, FP64 (%.1f s)" % (len(pick), cpairs, ct))
         for p, r in res.items():
-            sel = np.concatenate([np.arange(b.offsets[k], b.offsets[k + 1]) for k in pick])
-            ref = np.concatenate([refs[k] for k in pick])
-            errors[p] = errors_of(metrics, r["acc"][sel], None, ref, None)
+            raT, rpT = refs(r["xT"])
+            errors[p] = {"step0": errors_of(metrics, r["a0"][sel], r["p0"][sel], ra0, rp0),
+                         "after_timed_steps": errors_of(metrics, r["aT"][sel], r["pT"][sel],
+                                                        raT, rpT),
+                         "systems": len(pick), "smallest_n": int(min(b.sizes[k] for k in pick))}
     head = next(iter(res))
     r0 = res[head]
     return {
@@ -473,12 +622,16 @@ def bench_clusters(args, torch, w):
         "cpu_baseline": cpu,
         "modes": {p: {"value": pairs * args.steps / r["wall"],
                       "ms_per_step": r["wall"] / args.steps * 1e3,
-                      "force_kernel_ms": r["kernel_ms"], "errors": errors.get(p)}
-                  for p, r in res.items()},
+                      "force_kernel_ms": r["kernel_ms"],
+                      **{"roofline_" + k: v for k, v in
+                         fractions("gravity", pairs, r["kernel_ms"]).items()
+                         if k in ("frac", "issue_frac")},
+                      "errors": errors.get(p)} for p, r in res.items()},
     }
 
 
-def bench_adjoint(args, torch, w):
+def bench_adjoint(args, torch, w, big=True):
+    """N = 16384 loss and gradient through a 32-step checkpointed KDK rollout."""
     from paper_astro_ph_0703100_amd import _lib, api, autograd, ics, metrics
     n = w.n
     x0, v0, mass = ics.plummer(n, seed=w.seed)
@@ -514,41 +667,46 @@ def bench_adjoint(args, torch, w):
     _, kms = timer.run(lambda: _lib.nbody_force_vjp(n, p32.data_ptr(), m32.data_ptr(), eps,
                                                     g.data_ptr(), None, gx.data_ptr(),
                                                     gm.data_ptr(), opts, sp), 8, warmup=args.warmup)
-    # The same kernel on the N = 131072 sphere, where the grid holds many rounds of blocks.
-    nb = 131072
-    xb, _, mb = ics.plummer(nb, seed=2, velocities=False)
-    pb = torch.from_numpy(np.ascontiguousarray(xb.T.astype(np.float32))).to(dev)
-    mbt = torch.from_numpy(mb.astype(np.float32)).to(dev)
-    gb = torch.from_numpy(np.random.default_rng(2).standard_normal((3, nb))).to(dev)
-    gxb = torch.empty((3, nb), dtype=torch.float64, device=dev)
-    gmb = torch.empty(nb, dtype=torch.float64, device=dev)
-    eb = float(np.float32(ics.plummer_131072_eps(nb)))
-    _, kmb = timer.run(lambda: _lib.nbody_force_vjp(nb, pb.data_ptr(), mbt.data_ptr(), eb,
-                                                    gb.data_ptr(), None, gxb.data_ptr(),
-                                                    gmb.data_ptr(), opts, sp), 3, warmup=args.warmup)
-    big = roofline("adjoint", float(nb) * nb, float(np.mean(kmb)), "tile_kernel<Adjoint>")
+    extra = {}
+    if big:
+        # The same kernel on the N = 131072 sphere, where the grid holds many rounds of blocks.
+        nb = 131072
+        xb, _, mb = ics.plummer(nb, seed=2, velocities=False)
+        pb = torch.from_numpy(np.ascontiguousarray(xb.T.astype(np.float32))).to(dev)
+        mbt = torch.from_numpy(mb.astype(np.float32)).to(dev)
+        gb = torch.from_numpy(np.random.default_rng(2).standard_normal((3, nb))).to(dev)
+        gxb = torch.empty((3, nb), dtype=torch.float64, device=dev)
+        gmb = torch.empty(nb, dtype=torch.float64, device=dev)
+        eb = float(np.float32(ics.plummer_131072_eps(nb)))
+        _, kmb = timer.run(lambda: _lib.nbody_force_vjp(nb, pb.data_ptr(), mbt.data_ptr(), eb,
+                                                        gb.data_ptr(), None, gxb.data_ptr(),
+                                                        gmb.data_ptr(), opts, sp), 3,
+                           warmup=args.warmup)
+        extra["adjoint_kernel_131072"] = fractions("adjoint", float(nb) * nb, float(np.mean(kmb)))
     pairs_step = float(n) * n * 2 * (w.steps + 1)
-    print("bench: rollout+gradient %.3f ms/step, adjoint kernel %.3f ms (N=%d: %.3f ms)" %
-          (wall / args.steps * 1e3, np.mean(kms), nb, np.mean(kmb)), file=sys.stderr, flush=True)
+    print("bench: rollout+gradient %.3f ms/step, adjoint kernel %.3f ms" %
+          (wall / args.steps * 1e3, np.mean(kms)), file=sys.stderr, flush=True)
     cpu, errors = None, {}
     if not args.no_cpu_baseline:
         import oracle
         t0 = time.perf_counter()
         lo, rx, rv, rm = oracle.rollout_loss_grad(x0, v0, m64, eps, w.dt, w.steps, y)
         ct = time.perf_counter() - t0
-        cpu = {"value": pairs_step / ct, "unit": "pair-interactions/s", "cores": oracle.threads(),
-               "kind": "oracle", "sample": "the whole loss and gradient (%d forward + %d adjoint "
-                                           "evaluations of %d^2 pairs), FP64 (%.1f s)"
-                                           % (w.steps + 1, w.steps + 1, n, ct)}
-        g1 = np.random.default_rng(w.seed + 2000).standard_normal((4096, 3))
-        one_thread(cpu, lambda: oracle.vjp(x0[:4096], m64[:4096], eps, g1), 4096.0 ** 2,
-                   "one adjoint evaluation on the first 4096 particles")
+        cpu = cpu_entry(pairs_step / ct,
+                        "the whole loss and gradient (%d forward + %d adjoint evaluations of "
+                        "%d^2 pairs), FP64 (%.1f s)" % (w.steps + 1, w.steps + 1, n, ct))
+        if big:
+            g1 = np.random.default_rng(w.seed + 2000).standard_normal((4096, 3))
+            one_thread(cpu, lambda: oracle.vjp(x0[:4096], m64[:4096], eps, g1), 4096.0 ** 2,
+                       "one adjoint evaluation on the first 4096 particles")
         loss, gxg, gvg, gmg = state["g"]
         errors["comp"] = {
             "loss_rel": abs(loss - lo) / abs(lo),
             "grad_x0_normwise": metrics.rel_errors(gxg.cpu().numpy().T, rx)["normwise"],
             "grad_v0_normwise": metrics.rel_errors(gvg.cpu().numpy().T, rv)["normwise"],
-            "grad_m_normwise": metrics.rel_errors(gmg.cpu().numpy(), rm)["normwise"]}
+            "grad_m_normwise": metrics.rel_errors(gmg.cpu().numpy(), rm)["normwise"],
+            "oracle_pinned_by": "central FP64 finite differences on this workload (64 position "
+                                "coordinates, 16 masses; CPU slow test)"}
     return {
         "value": pairs_step * args.steps / wall, "ms_per_step": wall / args.steps * 1e3,
         "config": {"workload": w.name, "n": n, "eps": eps, "dt": w.dt, "steps": w.steps,
@@ -560,10 +718,10 @@ def bench_adjoint(args, torch, w):
                              "tile_kernel<Adjoint> (+ finalize)"),
         "cpu_baseline": cpu,
         "modes": {"comp": {"value": pairs_step * args.steps / wall,
-                           "adjoint_kernel_ms": float(np.mean(kms)),
+                           "ms_per_step": wall / args.steps * 1e3,
+                           **fractions("adjoint", float(n) * n, float(np.mean(kms))),
                            "errors": errors.get("comp")}},
-        "adjoint_kernel_131072": {"kernel_ms": big["kernel_ms"], "frac": big["frac"],
-                                  "pairs_per_s": float(nb) * nb / (big["kernel_ms"] * 1e-3)},
+        **extra,
     }
 
 
@@ -584,7 +742,7 @@ def bench_shard(args, torch, w):
     timer = Timer(torch)
     pairs = float(ni) * float(n)
     res = {}
-    for precision in [s for s in args.modes.split(",") if s]:
+    for precision in modes_of(args):
         opts = api.make_opts(precision=precision)
         call = lambda: _lib.nbody_force_ij(ni, pi.data_ptr(), None, n, pj.data_ptr(), m.data_ptr(),
                                            eps, acc.data_ptr(), pot.data_ptr(), opts, sp)
@@ -603,10 +761,9 @@ def bench_shard(args, torch, w):
         t0 = time.perf_counter()
         ra, rp = oracle.force_ij(x64, m32.astype(np.float64), x64[idx], eps)
         ct = time.perf_counter() - t0
-        cpu = {"value": k * float(n) / ct, "unit": "pair-interactions/s",
-               "cores": oracle.threads(), "kind": "oracle",
-               "sample": "force+potential of %s i-particles of the shard from all %d, "
-                         "FP64 (%.1f s)" % ("all %d" % k if k == ni else "%d sampled" % k, n, ct)}
+        cpu = cpu_entry(k * float(n) / ct,
+                        "force+potential of %s i-particles of the shard from all %d, FP64 "
+                        "(%.1f s)" % ("all %d" % k if k == ni else "%d sampled" % k, n, ct))
         i1 = idx[::8]
         one_thread(cpu, lambda: oracle.force_ij(x64, m32.astype(np.float64), x64[i1], eps),
                    float(i1.size) * n, "%d of those i-particles" % i1.size)
@@ -627,8 +784,7 @@ def bench_shard(args, torch, w):
         "cpu_baseline": cpu,
         "modes": {p: {"value": pairs * args.steps / r["wall"],
                       "ms_per_step": r["wall"] / args.steps * 1e3,
-                      "kernel_ms": r["kernel_ms"],
-                      "roofline_frac": pairs / (r["kernel_ms"] * 1e-3) / peak_pairs("gravity"),
+                      **fractions("gravity", pairs, r["kernel_ms"]),
                       "errors": errors.get(p)} for p, r in res.items()},
     }
 
@@ -653,7 +809,7 @@ def bench_jerk(args, torch, w):
     pairs = float(n) * float(n)
     dt = w.dt or 1.0 / 256
     res = {}
-    for precision in [s for s in args.modes.split(",") if s]:
+    for precision in modes_of(args):
         opts = api.make_opts(precision=precision)
         xs, vs = x.clone(), v.clone()
         ha, hj = api.hermite(xs, vs, m, eps, dt, 0, precision=precision)
@@ -683,10 +839,9 @@ def bench_jerk(args, torch, w):
         t0 = time.perf_counter()
         ra, rj, rp = oracle.force_jerk(pos, vel, m32.astype(np.float64), eps, idx=idx)
         ct = time.perf_counter() - t0
-        cpu = {"value": k * float(n) / ct, "unit": "pair-interactions/s",
-               "cores": oracle.threads(), "kind": "oracle",
-               "sample": "force+jerk+potential of %d sampled i-particles from all %d, FP64 "
-                         "(%.1f s)" % (k, n, ct)}
+        cpu = cpu_entry(k * float(n) / ct,
+                        "force+jerk+potential of %d sampled i-particles from all %d, FP64 "
+                        "(%.1f s)" % (k, n, ct))
         i1 = idx[::16]
         one_thread(cpu, lambda: oracle.force_jerk(pos, vel, m32.astype(np.float64), eps, idx=i1),
                    float(i1.size) * n, "%d of those i-particles" % i1.size)
@@ -712,8 +867,7 @@ def bench_jerk(args, torch, w):
         "cpu_baseline": cpu,
         "modes": {p: {"value": pairs * args.steps / r["wall"],
                       "ms_per_step": r["wall"] / args.steps * 1e3,
-                      "jerk_kernel_ms": r["kernel_ms"],
-                      "roofline_frac": pairs / (r["kernel_ms"] * 1e-3) / peak_pairs("jerk"),
+                      **fractions("jerk", pairs, r["kernel_ms"]),
                       "errors": errors.get(p)} for p, r in res.items()},
         "gflops_60": pairs * 60 / (r0["kernel_ms"] * 1e-3) / 1e9,
     }
@@ -743,7 +897,7 @@ def bench_active(args, torch, w):
     timer = Timer(torch)
     pairs = float(ni) * float(n)
     res = {}
-    for precision in [s for s in args.modes.split(",") if s]:
+    for precision in modes_of(args):
         opts = api.make_opts(precision=precision)
         call = lambda: _lib.nbody_force_jerk_ij(ni, pi.data_ptr(), vi.data_ptr(), n, pj.data_ptr(),
                                                 vj.data_ptr(), m.data_ptr(), eps, acc.data_ptr(),
@@ -765,10 +919,9 @@ def bench_active(args, torch, w):
         t0 = time.perf_counter()
         ra, rj, rp = oracle.force_jerk_ij(x64, v64, mj, x64[sel], v64[sel], eps)
         ct = time.perf_counter() - t0
-        cpu = {"value": k * float(n) / ct, "unit": "pair-interactions/s",
-               "cores": oracle.threads(), "kind": "oracle",
-               "sample": "force+jerk+potential of %d of the active particles from all %d, FP64 "
-                         "(%.1f s)" % (k, n, ct)}
+        cpu = cpu_entry(k * float(n) / ct,
+                        "force+jerk+potential of %d of the active particles from all %d, FP64 "
+                        "(%.1f s)" % (k, n, ct))
         s1 = sel[::16]
         one_thread(cpu, lambda: oracle.force_jerk_ij(x64, v64, mj, x64[s1], v64[s1], eps),
                    float(s1.size) * n, "%d of those i-particles" % s1.size)
@@ -794,10 +947,51 @@ def bench_active(args, torch, w):
         "cpu_baseline": cpu,
         "modes": {p: {"value": pairs * args.steps / r["wall"],
                       "ms_per_step": r["wall"] / args.steps * 1e3,
-                      "kernel_ms": r["kernel_ms"],
-                      "roofline_frac": pairs / (r["kernel_ms"] * 1e-3) / peak_pairs("jerk"),
+                      **fractions("jerk", pairs, r["kernel_ms"]),
                       "errors": errors.get(p)} for p, r in res.items()},
     }
+
+
+BENCHES = {"plummer_131072": bench_plummer, "plummer_2048": bench_small,
+           "stress_1m": bench_stress, "clusters_2048": bench_clusters,
+           "adjoint_16384": bench_adjoint, "jerk_131072": bench_jerk,
+           "shard8_131072": bench_shard, "active8_131072": bench_active}
+
+
+def compact(body):
+    """The per-configuration entry of the default line: step time, pair rate, both roofline
+    fractions of the dominant kernel, and the accuracy against the oracle."""
+    roof = body["roofline"]
+    out = {"workload": body["config"]["workload"], "step": body["config"]["step"],
+           "ms_per_step": body["ms_per_step"], "pairs_per_s": body["value"],
+           "kernel": roof["kernel"], "kernel_ms": roof["kernel_ms"],
+           "roofline_frac": roof["frac"], "issue_frac": roof["issue_model"]["frac"],
+           "modes": {k: {kk: vv for kk, vv in v.items() if kk != "value"}
+                     for k, v in body["modes"].items()},
+           "oracle_sample": (body.get("cpu_baseline") or {}).get("sample")}
+    for key in ("error_split", "adjoint_kernel_131072"):
+        if body.get(key) is not None:
+            out[key] = body[key]
+    return out
+
+
+def run_configs(args, torch):
+    """Every configuration of the workload set besides the headline, in compact form."""
+    from paper_astro_ph_0703100_amd import ics
+    out = {}
+    for name in CONFIG_WORKLOADS:
+        sub = parse(["--steps", "4" if name != "plummer_2048" else "200",
+                     "--modes", "comp,plain,fp64red" if name != "adjoint_16384" else "comp"]
+                    + (["--no-cpu-baseline"] if args.no_cpu_baseline else []))
+        t0 = time.perf_counter()
+        fn = BENCHES[name]
+        body = fn(sub, torch, ics.WORKLOADS[name], big=False) if name == "adjoint_16384" \
+            else fn(sub, torch, ics.WORKLOADS[name])
+        out[name] = compact(body)
+        out[name]["bench_seconds"] = time.perf_counter() - t0
+        print("bench: config %s done (%.1f s)" % (name, out[name]["bench_seconds"]),
+              file=sys.stderr, flush=True)
+    return out
 
 
 def main():
@@ -823,18 +1017,17 @@ def main():
         del src, dst
 
     w = ics.WORKLOADS[args.workload]
-    fn = {"plummer_131072": bench_plummer, "plummer_2048": bench_plummer,
-          "stress_1m": bench_stress, "clusters_2048": bench_clusters,
-          "adjoint_16384": bench_adjoint, "jerk_131072": bench_jerk,
-          "shard8_131072": bench_shard, "active8_131072": bench_active}[w.name]
-    body = fn(args, torch, w)
+    body = BENCHES[w.name](args, torch, w)
+    warmed = WARMED[0] if WARMED else args.warmup
+    if w.name == "plummer_131072" and not args.no_configs:
+        body["configs"] = run_configs(args, torch)
     line = {
         "metric": METRIC if w.name == "plummer_131072" else "pair interactions/s, " + w.name,
         "value": body["value"],
         "unit": "pair-interactions/s",
         "n_gpus": 1,
         "steps": args.steps,
-        "warmup": WARMED[0] if WARMED else args.warmup,
+        "warmup": warmed,
         "ms_per_step": body["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",

@@ -24,8 +24,11 @@
  *   - Scratch memory: if opts->workspace is NULL the library uses a per-device
  *     buffer it allocates and grows on demand (calls on several streams of one
  *     device that overlap in time then race; give each stream its own workspace).
- *     While a stream is being captured into a HIP graph the library never
- *     allocates: a missing or too small workspace returns NBODY_ECAPTURE.
+ *     A call on a stream that is being captured into a HIP graph must pass
+ *     opts->workspace (at least the nbody_workspace_size* bytes of that call, kept
+ *     alive as long as the graph): with a NULL workspace it returns NBODY_ECAPTURE
+ *     and enqueues nothing, since a later call may reallocate the library's buffer
+ *     under the recorded graph.  A too small workspace returns NBODY_EINVAL.
  *   - Errors: a negative status; nbody_last_error() returns a message for the
  *     calling thread.  Invalid arguments are detected before anything is enqueued.
  */
@@ -50,7 +53,7 @@ typedef int32_t nbody_status;
 #define NBODY_EINVAL (-1)      /* bad size, NULL pointer, eps, offsets or option   */
 #define NBODY_ENOMEM (-2)      /* device allocation failed                         */
 #define NBODY_EHIP (-3)        /* HIP runtime error (message has the HIP text)     */
-#define NBODY_ECAPTURE (-4)    /* would allocate while the stream is capturing     */
+#define NBODY_ECAPTURE (-4)    /* stream is capturing and no workspace was given    */
 #define NBODY_EUNSUPPORTED (-5)/* option combination not built                     */
 
 /* Accumulation of the pair terms of one i-particle (Sec. 2.2.2 and Sec. 3.4). */
@@ -95,8 +98,9 @@ NBODY_API const char *nbody_last_error(void);
 /* Library version string. */
 NBODY_API const char *nbody_version(void);
 
-/* Bytes of scratch that nbody_force*, nbody_force_vjp* and nbody_leapfrog* need for
- * n particles with these options (the batched plan reports its own). */
+/* Bytes of scratch that nbody_force, nbody_force_ex, nbody_force_f64 and
+ * nbody_leapfrog need for n particles with these options (0 for n <= 0 or invalid
+ * options; the batched plan owns its own). */
 NBODY_API size_t nbody_workspace_size(int64_t n, const nbody_opts *opts);
 
 /* ------------------------------------------------------------------------------
@@ -107,9 +111,10 @@ NBODY_API size_t nbody_workspace_size(int64_t n, const nbody_opts *opts);
  *   eps   softening length (> 0); the kernel uses fp32(eps * eps)
  *   acc   double [3][n], accelerations (written)
  *   pot   double [n] potentials (written), or NULL to skip them
- * nbody_force uses the default options.  The j == i pair contributes nothing to
- * acc (its separation is exactly zero) and its -m_i/eps is removed from phi in the
- * FP64 reduction unless opts->self_pot is 1.
+ * nbody_force uses the default options.  The j == i pair is left out of every sum
+ * (the pair kernel hands it a massless copy of the particle, which adds exactly
+ * zero); with opts->self_pot = 1 the FP64 reduction adds -m_i/eps, formed in FP64,
+ * to phi.
  * ---------------------------------------------------------------------------- */
 NBODY_API nbody_status nbody_force(int64_t n, const float *pos, const float *mass, float eps,
                          double *acc, double *pot, void *stream);
@@ -153,8 +158,8 @@ NBODY_API size_t nbody_workspace_size_ij(int64_t ni, int64_t nj, const nbody_opt
  * (Sec. 4.1).  With d = x_j - x_i, w = v_j - v_i, s^2 = |d|^2 + eps^2:
  *   a_i = sum m_j d / s^3,  jerk_i = sum m_j (w / s^3 - 3 (d.w) d / s^5),
  *   phi_i = -sum m_j / s,
- * all i against all j of one system, j == i excluded as in nbody_force (self_pot = 1
- * keeps -m_i/eps in phi).
+ * all i against all j of one system, j == i left out as in nbody_force (self_pot = 1
+ * adds -m_i/eps to phi).
  *   n      particles, 0 <= n < 2^30
  *   pos    float [3][n], vel float [3][n], mass float [n] (read)
  *   eps    softening length (> 0, eps^2 a normal float)
@@ -291,6 +296,11 @@ NBODY_API nbody_status nbody_force_vjp_f64(int64_t n, const double *pos64, const
                                            float eps, const double *g_acc, const double *g_pot,
                                            double *grad_pos, double *grad_mass,
                                            const nbody_opts *opts, void *stream);
+/* Bytes of scratch that nbody_force_vjp and nbody_force_vjp_f64 need (the adjoint's
+ * own launch shape), and that nbody_leapfrog_adjoint needs (3n doubles more, for the
+ * cotangent of the accelerations).  0 for n <= 0 or invalid options. */
+NBODY_API size_t nbody_workspace_size_vjp(int64_t n, const nbody_opts *opts);
+NBODY_API size_t nbody_workspace_size_adjoint(int64_t n, const nbody_opts *opts);
 
 /* Reverse pass of nsteps KDK steps (nbody_leapfrog) from the checkpoints it stored.
  *   traj   double [nsteps+1][3][n]: x_0 .. x_nsteps (read)
@@ -298,7 +308,9 @@ NBODY_API nbody_status nbody_force_vjp_f64(int64_t n, const double *pos64, const
  *   vbar   double [3][n]: on entry dL/dv_nsteps, on exit dL/dv_0
  *   mbar   double [n] or NULL: dL/dm (through the dynamics) is ADDED to it
  * The cotangents of a(x_t) from the two kicks that use it are summed before one VJP
- * (nbody_force_vjp_f64 with the same options) per checkpoint. */
+ * (nbody_force_vjp_f64 with the same options) per checkpoint.  nsteps = 0 leaves
+ * xbar, vbar and mbar as they are (the rollout is the identity).  Scratch:
+ * nbody_workspace_size_adjoint bytes. */
 NBODY_API nbody_status nbody_leapfrog_adjoint(int64_t n, const double *traj, const float *mass,
                                               float eps, double dt, int32_t nsteps, double *xbar,
                                               double *vbar, double *mbar, const nbody_opts *opts,

@@ -97,6 +97,8 @@ SIGNATURES = {
     "nbody_force_vjp": (_I32, [_I64, _P, _P, _F, _P, _P, _P, _P, _OPTS, _P]),
     "nbody_force_vjp_f64": (_I32, [_I64, _P, _P, _F, _P, _P, _P, _P, _OPTS, _P]),
     "nbody_leapfrog_adjoint": (_I32, [_I64, _P, _P, _F, _D, _I32, _P, _P, _P, _OPTS, _P]),
+    "nbody_workspace_size_vjp": (ctypes.c_size_t, [_I64, _OPTS]),
+    "nbody_workspace_size_adjoint": (ctypes.c_size_t, [_I64, _OPTS]),
     "nbody_plan_create_batched": (_I32, [_I32, ctypes.POINTER(_I64), _OPTS, ctypes.POINTER(_P)]),
     "nbody_plan_destroy": (None, [_P]),
     "nbody_plan_info": (_I32, [_P, ctypes.POINTER(_I64)]),
@@ -243,6 +245,14 @@ def nbody_graph_create_hermite(n, pos64, vel64, mass, eps, dt, nsteps, acc, jerk
 
 def nbody_workspace_size_hermite(n: int, opts: nbody_opts | None) -> int:
     return int(load().nbody_workspace_size_hermite(n, _opt_ref(opts)))
+
+
+def nbody_workspace_size_vjp(n: int, opts: nbody_opts | None) -> int:
+    return int(load().nbody_workspace_size_vjp(n, _opt_ref(opts)))
+
+
+def nbody_workspace_size_adjoint(n: int, opts: nbody_opts | None) -> int:
+    return int(load().nbody_workspace_size_adjoint(n, _opt_ref(opts)))
 
 
 def _opt_ref(opts):

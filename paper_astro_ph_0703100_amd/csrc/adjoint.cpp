@@ -34,7 +34,7 @@ nbody_status vjp_f32_core(int64_t n, const float *pos, const float *mass, float 
                g_pot, (int)n,  cfg.seg_len, e2,   part,  cfg.npad};
     nbody_status st = launch_vjp(cfg, o.precision, va, grad_mass != nullptr, s);
     if (st) return st;
-    VjpFinalizeArgs fa{part,     cfg.nseg,  cfg.npad, (int)n, g_pot, e2, grad_pos, grad_mass,
+    VjpFinalizeArgs fa{part, cfg.nseg, cfg.npad, (int)n, g_pot, grad_pos, grad_mass,
                        accumulate ? 1 : 0};
     return launch_vjp_finalize(o.precision, fa, s);
 }
@@ -57,7 +57,7 @@ nbody_status vjp_f64_core(int64_t n, const double *pos64, const float *mass, flo
         VjpTileArgs va{pos64, pos64 + n, pos64 + 2 * n, mass, g_acc, g_acc + n, g_acc + 2 * n,
                        g_pot, (int)n, cfg.seg_len, e2, ws.part, cfg.npad, centres, itile};
         if ((st = launch_vjp_tile(cfg, o.precision, va, grad_mass != nullptr, s))) return st;
-        VjpFinalizeArgs fa{ws.part, cfg.nseg, cfg.npad, (int)n, g_pot, e2, grad_pos, grad_mass,
+        VjpFinalizeArgs fa{ws.part, cfg.nseg, cfg.npad, (int)n, g_pot, grad_pos, grad_mass,
                            accumulate ? 1 : 0};
         return launch_vjp_finalize(o.precision, fa, s);
     }
@@ -78,6 +78,19 @@ nbody_status vjp_f64_core(int64_t n, const double *pos64, const float *mass, flo
 using namespace nbody;
 
 extern "C" {
+
+size_t nbody_workspace_size_vjp(int64_t n, const nbody_opts *opts) {
+    nbody_opts o = resolve_opts(opts);
+    if (n <= 0) return 0;
+    TileCfg c;
+    if (choose_cfg(KERNEL_VJP, n, o.precision, o, &c) != NBODY_OK) return 0;
+    return vjp_f64_bytes(n, c, o.precision);
+}
+
+size_t nbody_workspace_size_adjoint(int64_t n, const nbody_opts *opts) {
+    const size_t base = nbody_workspace_size_vjp(n, opts);
+    return base ? base + sizeof(double) * 3 * (size_t)n : 0;
+}
 
 nbody_status nbody_force_vjp(int64_t n, const float *pos, const float *mass, float eps,
                              const double *g_acc, const double *g_pot, double *grad_pos,
@@ -127,7 +140,9 @@ nbody_status nbody_leapfrog_adjoint(int64_t n, const double *traj, const float *
     if (misaligned(traj) || misaligned(mass) || misaligned(xbar) || misaligned(vbar) ||
         misaligned(mbar))
         return set_error(NBODY_EINVAL, "misaligned array argument");
-    if (n == 0) return NBODY_OK;
+    // Zero steps: the rollout is the identity, so dL/dx_0 = xbar and dL/dv_0 = vbar as
+    // given, and the masses get nothing.
+    if (n == 0 || nsteps == 0) return NBODY_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
     TileCfg cfg;
     if ((st = choose_cfg(KERNEL_VJP, n, o.precision, o, &cfg))) return st;

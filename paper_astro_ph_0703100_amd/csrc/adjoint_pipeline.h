@@ -8,12 +8,9 @@
 //              w_kj = m_k g_j - m_j g_k
 //           =  sum_{j != k} [ w / s^3 - (q / s^3 + 3 (d . w) / s^5) d ],  q = m_k p_j + m_j p_k
 //   dL/dm_k = -sum_{j != k} [ (g_j . d) / s^3 + p_j / s ].
-// For j == k, d = 0 exactly and w is the difference of two identically rounded
-// products (no FMA contraction), so that pair adds exactly zero to dL/dx_k; its term
-// fl(p_k rsq(eps^2)) in dL/dm_k is rounded on its own and removed exactly in the FP64
-// finalize (the rounding it caused inside an FP32 block partial is at most about
-// kBlockJ u (|p_k| / eps + sum_j |p_j| / s)).
-// 38 VALU operations and one v_rsq_f32 per pair.
+// The engine hands the j == k pair a record with no mass and no cotangents (null_j):
+// with d = 0 exactly, w = m_k * 0 - 0 * g_k = 0, q = 0 and p_j = 0 it adds exactly
+// zero to both sums.  38 VALU operations and one v_rsq_f32 per pair.
 #pragma once
 
 #include "tile_engine.h"
@@ -53,6 +50,12 @@ struct Adjoint {
     static __device__ __forceinline__ void pad_j(float (&r)[8]) {
 #pragma unroll
         for (int c = 0; c < 8; ++c) r[c] = 0.0f;
+    }
+    // The j == k pair: the same position, with mass and both cotangents zero.
+    static constexpr bool kSelf = true;
+    static __device__ __forceinline__ void null_j(float (&r)[8]) {
+#pragma unroll
+        for (int c = 3; c < 8; ++c) r[c] = 0.0f;
     }
 
     template <bool MASS>
@@ -96,7 +99,7 @@ struct Adjoint {
             float gd = j[4] * dx;
             gd = __builtin_fmaf(j[5], dy, gd);
             gd = __builtin_fmaf(j[6], dz, gd);
-            const float pr = j[7] * r;  // rounded on its own: its j == k value is removed exactly
+            const float pr = j[7] * r;
             acc[3] = __builtin_fmaf(gd, r3, acc[3]);
             acc[3] = acc[3] + pr;
         }
@@ -105,7 +108,7 @@ struct Adjoint {
 
 // The same on FP64 positions relative to the block's i-tile centre: i's and staged j's
 // are converted as fp32(x - c_I) while loaded (for j == k the two conversions are the
-// same operation, so d = 0 exactly).
+// same operation, so d = 0 exactly and the null record adds nothing).
 struct AdjointTile {
     static constexpr int kJWords = 8;
     static constexpr int kOut = 4;
@@ -136,6 +139,8 @@ struct AdjointTile {
         r[7] = a.gp ? (float)a.gp[j] : 0.0f;
     }
     static __device__ __forceinline__ void pad_j(float (&r)[8]) { Adjoint::pad_j(r); }
+    static constexpr bool kSelf = true;
+    static __device__ __forceinline__ void null_j(float (&r)[8]) { Adjoint::null_j(r); }
     template <bool MASS>
     static __device__ __forceinline__ void pair(const float *j, const IState &k, float eps2,
                                                 float (&acc)[4]) {

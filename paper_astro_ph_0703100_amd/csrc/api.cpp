@@ -64,13 +64,19 @@ bool stream_capturing(hipStream_t s) {
     return st != hipStreamCaptureStatusNone;
 }
 
-// Scratch of at least `need` bytes: the caller's buffer, or the per-device cache
-// (grown outside stream capture only).
+// Scratch of at least `need` bytes: the caller's buffer, or the per-device cache.  A
+// capturing stream must bring its own buffer: a graph that recorded the cache's address
+// would read and write freed memory after a later call grew (reallocated) the cache.
 nbody_status get_workspace(const nbody_opts &o, size_t need, hipStream_t s, void **out) {
     if (need == 0) {
         *out = o.workspace;
         return NBODY_OK;
     }
+    if (!o.workspace && stream_capturing(s))
+        return set_error(NBODY_ECAPTURE,
+                         "stream is capturing: pass opts->workspace (the library's cache may be "
+                         "reallocated after the capture, which would leave the graph with freed "
+                         "memory)");
     if (o.workspace) {
         if (o.workspace_bytes < need)
             return set_error(NBODY_EINVAL, "workspace too small: need " + std::to_string(need) +
@@ -89,10 +95,6 @@ nbody_status get_workspace(const nbody_opts &o, size_t need, hipStream_t s, void
         *out = w.ptr;
         return NBODY_OK;
     }
-    if (stream_capturing(s))
-        return set_error(NBODY_ECAPTURE,
-                         "stream is capturing and the library workspace is too small; pass "
-                         "opts->workspace (nbody_workspace_size bytes)");
     if (w.ptr) {
         // hipFree waits for the device, so no kernel still uses the old buffer.
         NBODY_HIP_CHECK(hipFree(w.ptr));
@@ -181,6 +183,15 @@ nbody_status check_common(int64_t n, const void *pos, const void *mass, float ep
     return NBODY_OK;
 }
 
+nbody_status check_force_f32(int64_t n, const float *pos, const float *mass, float eps,
+                             const double *acc, const double *pot, const nbody_opts &o) {
+    nbody_status st = check_common(n, pos, mass, eps, acc, o);
+    if (st) return st;
+    if (misaligned(pos) || misaligned(mass) || misaligned(acc) || misaligned(pot))
+        return set_error(NBODY_EINVAL, "misaligned array argument");
+    return NBODY_OK;
+}
+
 size_t f64_scratch_bytes(int64_t n, const TileCfg &cfg, int precision) {
     return partial_bytes(cfg, precision) + align_up(sizeof(float) * 3 * (size_t)n, 256) +
            align_up(centre_scratch_bytes(), 256);
@@ -197,8 +208,6 @@ F64Scratch f64_scratch_layout(void *ws, int64_t n, const TileCfg &cfg, int preci
     return r;
 }
 
-namespace {
-
 // Pair kernel + FP64 reduction on FP32 structure-of-arrays positions.
 nbody_status force_f32_core(int64_t n, const float *pos, const float *mass, float eps, double *acc,
                             double *pot, const nbody_opts &o, const TileCfg &cfg, void *ws,
@@ -207,12 +216,10 @@ nbody_status force_f32_core(int64_t n, const float *pos, const float *mass, floa
     PairArgs pa{pos, pos + n, pos + 2 * n, mass, (int)n, cfg.seg_len, e2, ws, cfg.npad};
     nbody_status st = launch_pair(cfg, o.precision, pot != nullptr, pa, s);
     if (st) return st;
-    FinalizeArgs fa{ws,   cfg.nseg, cfg.npad, (int)n, mass, e2, o.self_pot ? 0 : 1,
-                    acc, pot,      kick_v,   kick_h};
+    FinalizeArgs fa{ws, cfg.nseg, cfg.npad, (int)n, mass, eps, o.self_pot, acc, pot, kick_v,
+                    kick_h};
     return launch_finalize(o.precision, fa, s);
 }
-
-}  // namespace
 
 nbody_status force_f64_core(int64_t n, const double *pos64, const float *mass, float eps,
                             double *acc, double *pot, const nbody_opts &o, const TileCfg &cfg,
@@ -229,7 +236,7 @@ nbody_status force_f64_core(int64_t n, const double *pos64, const float *mass, f
         TilePairArgs ta{pos64, pos64 + n, pos64 + 2 * n, mass, (int)n, cfg.seg_len, e2,
                         ws.part, cfg.npad, centres, itile};
         if ((st = launch_pair_tile(cfg, o.precision, pot != nullptr, ta, s))) return st;
-        FinalizeArgs fa{ws.part, cfg.nseg, cfg.npad, (int)n, mass, e2, o.self_pot ? 0 : 1,
+        FinalizeArgs fa{ws.part, cfg.nseg, cfg.npad, (int)n, mass, eps, o.self_pot,
                         acc,     pot,      kick_v,   kick_h};
         return launch_finalize(o.precision, fa, s);
     }
@@ -274,13 +281,9 @@ size_t nbody_workspace_size(int64_t n, const nbody_opts *opts) {
 nbody_status nbody_force_ex(int64_t n, const float *pos, const float *mass, float eps, double *acc,
                             double *pot, const nbody_opts *opts, void *stream) {
     clear_error();
-    nbody_opts o;
-    nbody_opts_default(&o);
-    if (opts) o = *opts;
-    nbody_status st = check_common(n, pos, mass, eps, acc, o);
+    nbody_opts o = resolve_opts(opts);
+    nbody_status st = check_force_f32(n, pos, mass, eps, acc, pot, o);
     if (st) return st;
-    if (misaligned(pos) || misaligned(mass) || misaligned(acc) || misaligned(pot))
-        return set_error(NBODY_EINVAL, "misaligned array argument");
     if (n == 0) return NBODY_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
     TileCfg cfg;
@@ -345,7 +348,7 @@ nbody_status nbody_force_ij(int64_t ni, const float *pos_i, const float *eps_i, 
     IJPairArgs a{pos_i, pos_i + ni, pos_i + 2 * ni, eps_i, pos_j, pos_j + nj, pos_j + 2 * nj,
                  mass_j, (int)ni, (int)nj, cfg.seg_len, e2, ws, cfg.npad};
     if ((st = launch_pair_ij(cfg, o.precision, pot != nullptr, a, s))) return st;
-    FinalizeArgs fa{ws, cfg.nseg, cfg.npad, (int)ni, nullptr, e2, 0, acc, pot, nullptr, 0.0};
+    FinalizeArgs fa{ws, cfg.nseg, cfg.npad, (int)ni, nullptr, eps, 0, acc, pot, nullptr, 0.0};
     return launch_finalize(o.precision, fa, s);
 }
 

@@ -104,8 +104,8 @@ nbody_status batched_core(const nbody_plan *p, const float *pos, const float *ma
     BatchSched sc{p->items, p->nitems, p->counter, eps, p->part};
     nbody_status st = launch_batched_pair(p->ipl, p->jt, p->opts.precision, with_pot, grid, pa, sc, s);
     if (st) return st;
-    BatchFinalizeArgs fa{p->part, n,    p->sys_of, p->offsets, p->part_base, p->npad, p->nseg,
-                         eps,     mass, acc,       pot,        kick_v,       kick_h};
+    BatchFinalizeArgs fa{p->part, n,   p->sys_of, p->offsets, p->part_base, p->npad, p->nseg,
+                         acc,     pot, kick_v,    kick_h};
     return launch_batched_finalize(p->opts.precision, fa, s);
 }
 

@@ -4,8 +4,8 @@
 //   * pair work: the persistent work-queue launch of the gravity pipeline over the
 //     plan's cost-sorted items (one i-tile x one j-range of one system each);
 //   * finalize: per particle, the fixed-order FP64 sum of its system's segment
-//     partials, removal of the j == i potential term with the system's eps, and the
-//     optional fused leapfrog kick;
+//     partials (no j == i term: the pair kernel left it out) and the optional fused
+//     leapfrog kick;
 //   * per-system FP64 centres (one block per system, fixed-order reduction) and the
 //     conversion of FP64 positions to FP32 relative to them.
 #include "gravity.h"
@@ -25,12 +25,6 @@ __global__ __launch_bounds__(256) void batched_finalize_kernel(BatchFinalizeArgs
     const void *base = static_cast<const float *>(a.part) + a.part_base[k];
     double r[4];
     engine::sum_partials<4, MODE, 1>(base, a.nseg[k], (size_t)npad, (int)col, r);
-    const float e = a.eps[k];
-    const float self = a.m[p] * __builtin_amdgcn_rsqf(e * e);
-    if constexpr (MODE == NBODY_PLAIN)
-        r[3] = (double)((float)r[3] + self);
-    else
-        r[3] += (double)self;
     const size_t n = (size_t)a.total;
     a.acc[p] = r[0];
     a.acc[n + p] = r[1];

@@ -7,11 +7,8 @@ namespace {
 
 // Fixed-order sum of the segment partials (PLAIN in FP32, the other modes in FP64),
 // one thread per (particle, output) so that few particles with many segments still
-// fill the chip; then removal of the j == i potential term fl(m_i * rsq(eps^2)),
-// recomputed with the FP32 operations the pair body used for it (exact removal; the
-// rounding that term caused while it was in an FP32 partial is at most about
-// A * u * (m_i / eps + |phi_i|), A the FP32 additions that followed it: fewer than one
-// block in the FP64 and compensated modes).
+// fill the chip.  The partials hold no j == i term (the pair kernel left it out); with
+// include_self the potential gets -m_i / eps, formed in FP64.
 // With kick_v set, the velocity kick of a leapfrog step follows in FP64.
 // Grid: (ceil(n / 256), 4 outputs, or 3 without potentials).
 template <int MODE, int BATCH>
@@ -21,13 +18,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinalizeArgs a) {
     if (i >= a.n) return;
     double r = engine::sum_partial_output<4, MODE, BATCH>(a.part, a.nseg, (size_t)a.npad, i, c);
     if (c == 3) {
-        if (a.exclude_self) {
-            const float self = a.m[i] * __builtin_amdgcn_rsqf(a.eps2);
-            if constexpr (MODE == NBODY_PLAIN)
-                r = (double)((float)r + self);
-            else
-                r += (double)self;
-        }
+        if (a.include_self) r -= (double)a.m[i] / (double)a.eps;
         a.pot[i] = r;
         return;
     }

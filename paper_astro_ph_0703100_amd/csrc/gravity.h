@@ -9,9 +9,8 @@ namespace nbody {
 
 // One softened pair term: separation x_j - x_i, s^2 = |d|^2 + eps^2 as an FMA chain,
 // 1/s from the hardware reciprocal square root (about 1 ulp); a += m d / s^3 and
-// phi -= m / s with m / s rounded on its own.  13 VALU operations and one v_rsq_f32.
-// For j == i the separation is exactly zero, so that pair adds nothing to a and adds
-// -fl(m_i rsq(eps^2)) to phi, which the finalize removes.
+// phi -= m / s.  13 VALU operations and one v_rsq_f32.  The engine hands the j == i
+// pair a massless record (null_j), so it adds exactly zero to a and phi.
 template <bool POT>
 __device__ __forceinline__ void gravity_pair(const float *j, float xi, float yi, float zi,
                                              float eps2, float (&acc)[4]) {
@@ -57,6 +56,10 @@ struct Gravity {
     }
     // A massless particle at the origin adds exactly zero.
     static __device__ __forceinline__ void pad_j(float (&r)[4]) { r[0] = r[1] = r[2] = r[3] = 0.0f; }
+    // The j == i pair: the same place with no mass (its separation is exactly zero, so
+    // every term is +0 times a finite number).
+    static constexpr bool kSelf = true;
+    static __device__ __forceinline__ void null_j(float (&r)[4]) { r[3] = 0.0f; }
 
     template <bool POT>
     static __device__ __forceinline__ void pair(const float *j, const IState &i, float eps2,
@@ -70,7 +73,7 @@ struct Gravity {
 // staged for the tile are converted as fp32(x - c_I) while they are loaded, so the
 // FP32 pair arithmetic sees coordinates of the size of the tile, not of the system.
 // For the j == i pair both conversions are the same operation, so the separation is
-// still exactly zero.
+// still exactly zero and the massless null record adds nothing.
 struct GravityTile {
     static constexpr int kJWords = 4;
     static constexpr int kOut = 4;
@@ -96,6 +99,8 @@ struct GravityTile {
         r[3] = a.m[j];
     }
     static __device__ __forceinline__ void pad_j(float (&r)[4]) { Gravity::pad_j(r); }
+    static constexpr bool kSelf = true;
+    static __device__ __forceinline__ void null_j(float (&r)[4]) { Gravity::null_j(r); }
     template <bool POT>
     static __device__ __forceinline__ void pair(const float *j, const IState &i, float eps2,
                                                 float (&acc)[4]) {
@@ -138,6 +143,7 @@ struct GravityIJ {
         r[0] = r[1] = r[2] = 1e30f;
         r[3] = 0.0f;
     }
+    static constexpr bool kSelf = false;  // separate sets: every pair is summed
     template <bool POT>
     static __device__ __forceinline__ void pair(const float *j, const IState &i, float,
                                                 float (&acc)[4]) {

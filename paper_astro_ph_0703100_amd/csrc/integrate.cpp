@@ -16,14 +16,16 @@ namespace nbody {
 namespace {
 
 nbody_status check_leapfrog(int64_t n, const double *x, const double *v, const float *m, float eps,
-                            double dt, int32_t nsteps, const double *acc, const nbody_opts &o) {
+                            double dt, int32_t nsteps, const double *acc, const nbody_opts &o,
+                            const double *pot = nullptr, const double *traj = nullptr) {
     nbody_status st = check_common(n, x, m, eps, acc, o);
     if (st) return st;
     if (n > 0 && !v) return set_error(NBODY_EINVAL, "vel must not be NULL");
     if (nsteps < 0) return set_error(NBODY_EINVAL, "nsteps must be >= 0");
     if (!std::isfinite(dt))
         return set_error(NBODY_EINVAL, "dt must be finite");
-    if (misaligned(x) || misaligned(v) || misaligned(m) || misaligned(acc))
+    if (misaligned(x) || misaligned(v) || misaligned(m) || misaligned(acc) || misaligned(pot) ||
+        misaligned(traj))
         return set_error(NBODY_EINVAL, "misaligned array argument");
     return NBODY_OK;
 }
@@ -93,7 +95,7 @@ nbody_status nbody_leapfrog(int64_t n, double *pos64, double *vel64, const float
                             int32_t flags, const nbody_opts *opts, void *stream) {
     clear_error();
     nbody_opts o = resolve_opts(opts);
-    nbody_status st = check_leapfrog(n, pos64, vel64, mass, eps, dt, nsteps, acc, o);
+    nbody_status st = check_leapfrog(n, pos64, vel64, mass, eps, dt, nsteps, acc, o, pot, traj);
     if (st) return st;
     if (flags & ~NBODY_LF_INIT_ACC) return set_error(NBODY_EINVAL, "unknown flags");
     if (n == 0) return NBODY_OK;
@@ -115,7 +117,7 @@ nbody_status nbody_graph_create_leapfrog(int64_t n, double *pos64, double *vel64
     if (!out) return set_error(NBODY_EINVAL, "out must not be NULL");
     *out = nullptr;
     nbody_opts o = resolve_opts(opts);
-    nbody_status st = check_leapfrog(n, pos64, vel64, mass, eps, dt, nsteps, acc, o);
+    nbody_status st = check_leapfrog(n, pos64, vel64, mass, eps, dt, nsteps, acc, o, pot);
     if (st) return st;
     if (n == 0 || nsteps == 0) return set_error(NBODY_EINVAL, "graph needs n > 0 and nsteps > 0");
     hipStream_t user = static_cast<hipStream_t>(stream);

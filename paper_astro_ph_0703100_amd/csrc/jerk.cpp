@@ -60,7 +60,7 @@ nbody_status jerk_core(int64_t n, const float *pos, const float *vel, const floa
                (int)n, cfg.seg_len, e2, part, cfg.npad};
     nbody_status st = launch_jerk(cfg, o.precision, pot != nullptr, a, s);
     if (st) return st;
-    JerkFinalizeArgs fa{part, cfg.nseg, cfg.npad, (int)n, mass, e2, o.self_pot ? 0 : 1,
+    JerkFinalizeArgs fa{part, cfg.nseg, cfg.npad, (int)n, mass, eps, o.self_pot,
                         acc,  jerk,     pot};
     return launch_jerk_finalize(o.precision, fa, s);
 }
@@ -83,7 +83,7 @@ nbody_status jerk_f64_core(int64_t n, const double *pos64, const double *vel64, 
         JerkTileArgs a{pos64, pos64 + n, pos64 + 2 * n, mass, vel64, vel64 + n, vel64 + 2 * n,
                        (int)n, cfg.seg_len, e2, w.part, cfg.npad, cx, cv, itile};
         if ((st = launch_jerk_tile(cfg, o.precision, pot != nullptr, a, s))) return st;
-        JerkFinalizeArgs fa{w.part, cfg.nseg, cfg.npad, (int)n, mass, e2, o.self_pot ? 0 : 1,
+        JerkFinalizeArgs fa{w.part, cfg.nseg, cfg.npad, (int)n, mass, eps, o.self_pot,
                             acc,    jerk,     pot};
         return launch_jerk_finalize(o.precision, fa, s);
     }
@@ -241,7 +241,7 @@ nbody_status nbody_force_jerk_ij(int64_t ni, const float *pos_i, const float *ve
                  pos_j, pos_j + nj, pos_j + 2 * nj, mass_j, vel_j, vel_j + nj, vel_j + 2 * nj,
                  (int)ni, (int)nj, cfg.seg_len, e2, ws, cfg.npad};
     if ((st = launch_jerk_ij(cfg, o.precision, pot != nullptr, a, s))) return st;
-    JerkFinalizeArgs fa{ws, cfg.nseg, cfg.npad, (int)ni, nullptr, e2, 0, acc, jerk, pot};
+    JerkFinalizeArgs fa{ws, cfg.nseg, cfg.npad, (int)ni, nullptr, eps, 0, acc, jerk, pot};
     return launch_jerk_finalize(o.precision, fa, s);
 }
 

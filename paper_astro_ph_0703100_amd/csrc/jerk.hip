@@ -5,9 +5,9 @@
 namespace nbody {
 namespace {
 
-// One thread per (particle, output): fixed-order sums as in the force finalize, the
-// j == i potential term removed exactly.  Grid: (ceil(n / 256), 7 outputs, or 6
-// without potentials).
+// One thread per (particle, output): fixed-order sums as in the force finalize (the
+// partials hold no j == i term; with include_self phi gets -m_i / eps in FP64).
+// Grid: (ceil(n / 256), 7 outputs, or 6 without potentials).
 template <int MODE, int BATCH>
 __global__ __launch_bounds__(256) void jerk_finalize_kernel(JerkFinalizeArgs a) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -16,13 +16,7 @@ __global__ __launch_bounds__(256) void jerk_finalize_kernel(JerkFinalizeArgs a) 
     double r = engine::sum_partial_output<7, MODE, BATCH>(a.part, a.nseg, (size_t)a.npad, i, c);
     const size_t n = (size_t)a.n;
     if (c == 6) {
-        if (a.exclude_self) {
-            const float self = a.m[i] * __builtin_amdgcn_rsqf(a.eps2);
-            if constexpr (MODE == NBODY_PLAIN)
-                r = (double)((float)r + self);
-            else
-                r += (double)self;
-        }
+        if (a.include_self) r -= (double)a.m[i] / (double)a.eps;
         a.pot[i] = r;
     } else if (c < 3) {
         a.acc[c * n + i] = r;

@@ -16,8 +16,8 @@
 namespace nbody {
 namespace {
 
-// One pair term.  For j == i both d and w are exactly zero, so the pair adds nothing
-// to a and the jerk and -fl(m_i rsq(eps^2)) to phi, which the finalize removes.
+// One pair term.  The engine hands the j == i pair a massless record (null_j): with d
+// and w exactly zero and m = 0 it adds exactly zero to a, the jerk and phi.
 template <bool POT>
 __device__ __forceinline__ void jerk_pair(const float *j, float xi, float yi, float zi, float vxi,
                                           float vyi, float vzi, float eps2, float (&acc)[7]) {
@@ -82,6 +82,9 @@ struct GravityJerk {
 #pragma unroll
         for (int c = 0; c < 8; ++c) r[c] = 0.0f;
     }
+    // The j == i pair: same position and velocity, no mass.
+    static constexpr bool kSelf = true;
+    static __device__ __forceinline__ void null_j(float (&r)[8]) { r[3] = 0.0f; }
     template <bool POT>
     static __device__ __forceinline__ void pair(const float *j, const IState &i, float eps2,
                                                 float (&acc)[7]) {
@@ -123,6 +126,8 @@ struct GravityJerkTile {
         r[7] = 0.0f;
     }
     static __device__ __forceinline__ void pad_j(float (&r)[8]) { GravityJerk::pad_j(r); }
+    static constexpr bool kSelf = true;
+    static __device__ __forceinline__ void null_j(float (&r)[8]) { GravityJerk::null_j(r); }
     template <bool POT>
     static __device__ __forceinline__ void pair(const float *j, const IState &i, float eps2,
                                                 float (&acc)[7]) {
@@ -162,6 +167,7 @@ struct GravityJerkIJ {
 #pragma unroll
         for (int c = 3; c < 8; ++c) r[c] = 0.0f;
     }
+    static constexpr bool kSelf = false;  // separate sets: every pair is summed
     template <bool POT>
     static __device__ __forceinline__ void pair(const float *j, const IState &i, float eps2,
                                                 float (&acc)[7]) {

@@ -128,8 +128,8 @@ struct JerkFinalizeArgs {
     const void *part;
     int nseg, npad, n;
     const float *m;
-    float eps2;
-    int exclude_self;
+    float eps;
+    int include_self;  // 1: add the j == i potential term -m_i / eps (in FP64)
     double *acc;   // [3][n]
     double *jerk;  // [3][n]
     double *pot;   // [n] or nullptr
@@ -167,8 +167,6 @@ struct BatchFinalizeArgs {
     const int64_t *part_base;  // [nsys] word offset of each system's planes
     const int32_t *npad;       // [nsys]
     const int32_t *nseg;       // [nsys]
-    const float *eps;          // [nsys]
-    const float *m;
     double *acc;               // [3][total]
     double *pot;               // [total] or nullptr
     double *kick_v;            // [3][total] or nullptr
@@ -180,8 +178,8 @@ struct FinalizeArgs {
     const void *part;
     int nseg, npad, n;
     const float *m;
-    float eps2;
-    int exclude_self;  // 1: remove the j == i potential term
+    float eps;
+    int include_self;  // 1: add the j == i potential term -m_i / eps (in FP64)
     double *acc;       // [3][n]
     double *pot;       // [n] or nullptr
     double *kick_v;    // [3][n]: if not null, v += kick_h * a after a is written
@@ -218,7 +216,6 @@ struct VjpFinalizeArgs {
     const void *part;
     int nseg, npad, n;
     const double *gp;   // dL/dphi or nullptr
-    float eps2;
     double *grad_pos;   // [3][n]
     double *grad_mass;  // [n] or nullptr
     int accumulate;     // 1: add into grad_pos / grad_mass instead of overwriting
@@ -253,6 +250,14 @@ size_t align_up(size_t v, size_t a);
 nbody_status check_common(int64_t n, const void *pos, const void *mass, float eps,
                           const void *acc, const nbody_opts &o);
 nbody_opts resolve_opts(const nbody_opts *opts);
+// Argument checks of the FP32-position force entry points (before anything is enqueued).
+nbody_status check_force_f32(int64_t n, const float *pos, const float *mass, float eps,
+                             const double *acc, const double *pot, const nbody_opts &o);
+// Pair kernel + FP64 finalize on FP32 positions [3][n] with the partial sums in `ws`
+// (partial_bytes(cfg, o.precision) bytes); with kick_v set, v += kick_h * a follows.
+nbody_status force_f32_core(int64_t n, const float *pos, const float *mass, float eps, double *acc,
+                            double *pot, const nbody_opts &o, const TileCfg &cfg, void *ws,
+                            double *kick_v, double kick_h, hipStream_t s);
 
 // Scratch layout of one FP64-position force evaluation: partial sums, FP32 relative
 // positions [3][n] (or, with per-i-tile centres, the tile centres), and the partials of

@@ -12,9 +12,11 @@
 //     tile), the J-BAG / J-PACKING of Sec. 2.2;
 //   * every lane reads each j-record from LDS with broadcast 16-byte reads and runs
 //     the pair body for its IPL i-records;
-//   * the j == i pair is evaluated like any other: every term that carries the
-//     separation is exactly zero there, and the pipelines round the remaining
-//     (potential-type) self term on its own so their finalize can remove it exactly;
+//   * the j == i pair is left out of every sum (eq. (1) sums over the other
+//     particles): in the few j-tiles that hold some of the block's own i's (i- and
+//     j-sets the same, Op::kSelf), each lane swaps the record of its own particle
+//     for Op::null_j of it (same position, nothing that adds), by a compare and a
+//     select per pair; all other tiles run the plain pass;
 //   * accumulation (Sec. 2.2.2, eq. (2); Sec. 3.4):
 //       PLAIN   - one FP32 accumulator per output and (i, segment);
 //       FP64RED - FP32 partial over each block of min(Op::kBlockJ, JT) j's, added into FP64;
@@ -36,6 +38,10 @@
 //   static IState load_i(const Args&, const Ctx&, int i);
 //   static void load_j(const Args&, const Ctx&, int j, float (&r)[kJWords]);
 //   static void pad_j(float (&r)[kJWords]);  // a record that adds exactly zero
+//   static constexpr bool kSelf;             // i- and j-sets are one set (j == i exists)
+//   static void null_j(float (&r)[kJWords]); // (kSelf only) turns a j-record into one at
+//                                            // the same place that adds nothing: the
+//                                            // j == i pair then adds exactly zero
 //   template <bool FULL> static void pair(const float *jr, const IState&, float eps2,
 //                                         float (&acc)[kOut]);
 //   (FULL = false may skip the last output.)
@@ -58,12 +64,35 @@ __device__ __forceinline__ void two_sum(float &hi, float &lo, float b) {
     lo = lo + err;
 }
 
-// One LDS tile: all JT j-records against the lane's IPL i-records.
-template <class Op, int IPL, int JT, int MODE, bool FULL>
+// One pair of the lane's k-th i-record with j-record jr; with SELF, the record of the
+// lane's own particle (tile slot jj == self[k]) is replaced by Op::null_j of it.
+template <class Op, bool FULL, bool SELF>
+__device__ __forceinline__ void pair_k(const float *jr, int jj, int self_k,
+                                       const typename Op::IState &is, float eps2,
+                                       float (&acc)[Op::kOut]) {
+    if constexpr (SELF) {
+        float r[Op::kJWords];
+        float z[Op::kJWords];
+#pragma unroll
+        for (int w = 0; w < Op::kJWords; ++w) r[w] = z[w] = jr[w];
+        Op::null_j(z);
+        const bool own = jj == self_k;
+#pragma unroll
+        for (int w = 0; w < Op::kJWords; ++w) r[w] = own ? z[w] : r[w];
+        Op::template pair<FULL>(r, is, eps2, acc);
+    } else {
+        Op::template pair<FULL>(jr, is, eps2, acc);
+    }
+}
+
+// One LDS tile: all JT j-records against the lane's IPL i-records.  With SELF, self[k]
+// is the tile slot of the lane's k-th own particle (outside [0, JT) if not in it).
+template <class Op, int IPL, int JT, int MODE, bool FULL, bool SELF = false>
 __device__ __forceinline__ void tile_pass(const float4 *tl, const typename Op::IState (&is)[IPL],
                                           float eps2, float (&hs)[IPL][Op::kOut],
                                           float (&ls)[IPL][Op::kOut],
-                                          double (&ds)[IPL][Op::kOut]) {
+                                          double (&ds)[IPL][Op::kOut],
+                                          const int (&self)[IPL]) {
     constexpr int W = Op::kJWords;
     constexpr int NO = Op::kOut;
     auto read = [&](int jj, float (&jr)[W]) {
@@ -76,13 +105,17 @@ __device__ __forceinline__ void tile_pass(const float4 *tl, const typename Op::I
             jr[4 * v + 3] = q4.w;
         }
     };
+    // The pass with the self test runs on a few tiles only: a shorter unroll keeps its
+    // code small.
+    constexpr int kUnrollPlain = SELF ? 4 : 8;
     if constexpr (MODE == NBODY_PLAIN) {
-#pragma unroll 8
+#pragma unroll kUnrollPlain
         for (int jj = 0; jj < JT; ++jj) {
             float jr[W];
             read(jj, jr);
 #pragma unroll
-            for (int k = 0; k < IPL; ++k) Op::template pair<FULL>(jr, is[k], eps2, hs[k]);
+            for (int k = 0; k < IPL; ++k)
+                pair_k<Op, FULL, SELF>(jr, jj, self[k], is[k], eps2, hs[k]);
         }
     } else {
         constexpr int BJ = JT < Op::kBlockJ ? JT : Op::kBlockJ;
@@ -95,12 +128,14 @@ __device__ __forceinline__ void tile_pass(const float4 *tl, const typename Op::I
                 for (int c = 0; c < NO; ++c) bs[k][c] = -0.0f;
             // Unrolled 32 pairs deep: longer blocks loop over that body (a scalar
             // branch per 32 pairs) instead of growing the code and the build time.
-#pragma unroll 32
+            constexpr int kUnroll = SELF ? 8 : 32;
+#pragma unroll kUnroll
             for (int jj = 0; jj < BJ; ++jj) {
                 float jr[W];
                 read(jb + jj, jr);
 #pragma unroll
-                for (int k = 0; k < IPL; ++k) Op::template pair<FULL>(jr, is[k], eps2, bs[k]);
+                for (int k = 0; k < IPL; ++k)
+                    pair_k<Op, FULL, SELF>(jr, jb + jj, self[k], is[k], eps2, bs[k]);
             }
 #pragma unroll
             for (int k = 0; k < IPL; ++k)
@@ -178,6 +213,12 @@ __device__ __forceinline__ void block_work(const typename Op::Args &a, float4 (*
         }
     };
 
+    // Global index of the lane's k-th own particle (padding lanes of the last i-tile
+    // get indices >= n, whose j-slots hold padding records or nothing).
+    int own[IPL];
+#pragma unroll
+    for (int k = 0; k < IPL; ++k) own[k] = i0 + k * kTPB + tid;
+
     if (ntiles > 0) {
         fetch(0);
         store(0);
@@ -186,7 +227,19 @@ __device__ __forceinline__ void block_work(const typename Op::Args &a, float4 (*
     for (int t = 0; t < ntiles; ++t) {
         const int buf = t & 1;
         if (t + 1 < ntiles) fetch(t + 1);
-        tile_pass<Op, IPL, JT, MODE, FULL>(tile[buf], is, eps2, hs, ls, ds);
+        const int jt0 = j0 + t * JT;
+        int self[IPL];
+#pragma unroll
+        for (int k = 0; k < IPL; ++k) self[k] = own[k] - jt0;
+        if constexpr (Op::kSelf) {
+            // Uniform over the block: does this tile hold any of the block's own i's?
+            if (jt0 < i0 + kTPB * IPL && i0 < jt0 + JT)
+                tile_pass<Op, IPL, JT, MODE, FULL, true>(tile[buf], is, eps2, hs, ls, ds, self);
+            else
+                tile_pass<Op, IPL, JT, MODE, FULL, false>(tile[buf], is, eps2, hs, ls, ds, self);
+        } else {
+            tile_pass<Op, IPL, JT, MODE, FULL, false>(tile[buf], is, eps2, hs, ls, ds, self);
+        }
         if (t + 1 < ntiles) store(buf ^ 1);
         __syncthreads();
     }

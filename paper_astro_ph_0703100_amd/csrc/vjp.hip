@@ -6,8 +6,8 @@ namespace nbody {
 namespace {
 
 // One thread per (particle, output), as in the force finalize: fixed-order sums of the
-// segment partials, then dL/dx_k (outputs 0-2) or dL/dm_k with the j == k term removed
-// exactly (output 3).  Grid: (ceil(n / 256), 4 outputs, or 3 without dL/dm).
+// segment partials (which hold no j == k term), then dL/dx_k (outputs 0-2) or dL/dm_k
+// (output 3, the negated sum).  Grid: (ceil(n / 256), 4 outputs, or 3 without dL/dm).
 template <int MODE, int BATCH>
 __global__ __launch_bounds__(256) void vjp_finalize_kernel(VjpFinalizeArgs a) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -19,9 +19,7 @@ __global__ __launch_bounds__(256) void vjp_finalize_kernel(VjpFinalizeArgs a) {
         *g = a.accumulate ? *g + r : r;
         return;
     }
-    const float pk = a.gp ? (float)a.gp[k] : 0.0f;
-    const double self = (double)(pk * __builtin_amdgcn_rsqf(a.eps2));
-    const double gm = -(r - self);
+    const double gm = -r;
     a.grad_mass[k] = a.accumulate ? a.grad_mass[k] + gm : gm;
 }
 

@@ -192,6 +192,33 @@ def test_workspace_size_grows_with_n_and_mode():
     assert _lib.nbody_workspace_size(100000, o) < b
 
 
+def test_vjp_and_adjoint_workspace_sizes():
+    o = _lib.nbody_opts_default()
+    assert _lib.nbody_workspace_size_vjp(0, o) == 0
+    assert _lib.nbody_workspace_size_adjoint(-5, o) == 0
+    for n in (100, 16384, 131072):
+        v = _lib.nbody_workspace_size_vjp(n, o)
+        a = _lib.nbody_workspace_size_adjoint(n, o)
+        assert v > 0 and a == v + 3 * 8 * n
+    # The adjoint's own launch shape: an explicit j-split changes the VJP size only.
+    o.nseg = 8
+    assert _lib.nbody_workspace_size_vjp(16384, o) < _lib.nbody_workspace_size_vjp(
+        16384, _lib.nbody_opts_default())
+    o.nseg = 0
+    o.ipl = 3
+    assert _lib.nbody_workspace_size_vjp(16384, o) == 0
+
+
+def test_adjoint_rejects_a_too_small_workspace():
+    o = _lib.nbody_opts_default()
+    need = _lib.nbody_workspace_size_adjoint(1000, o)
+    o.workspace = FAKE * 256
+    o.workspace_bytes = need - 1
+    st = _lib.nbody_leapfrog_adjoint(1000, FAKE, FAKE, 0.1, 0.01, 3, FAKE, FAKE, None, o, None,
+                                     check=False)
+    assert st == _lib.NBODY_EINVAL and "workspace" in _lib.nbody_last_error()
+
+
 def test_zero_particles_is_a_noop_without_device_access():
     # n = 0 returns before any HIP call, even with NULL arrays.
     assert _lib.nbody_force(0, None, None, 0.1, None, None, None, check=False) == _lib.NBODY_OK
@@ -215,6 +242,8 @@ def test_leapfrog_rejects_invalid_arguments():
     assert call(flags=4) == _lib.NBODY_EINVAL
     assert call(eps=0.0) == _lib.NBODY_EINVAL
     assert call(x=FAKE + 4) == _lib.NBODY_EINVAL
+    assert call(pot=FAKE + 4) == _lib.NBODY_EINVAL
+    assert call(traj=FAKE + 4) == _lib.NBODY_EINVAL
     assert call(n=0, x=None, v=None, m=None, acc=None) == _lib.NBODY_OK
 
 
@@ -243,6 +272,9 @@ def test_vjp_and_adjoint_reject_invalid_arguments():
         assert f(10, FAKE, FAKE, 0.1, FAKE + 4, None, FAKE, None, o, None, check=False) == _lib.NBODY_EINVAL
         assert f(0, None, None, 0.1, None, None, None, None, o, None, check=False) == _lib.NBODY_OK
     adj = _lib.nbody_leapfrog_adjoint
+    # Zero steps: the cotangents pass through unchanged, nothing is enqueued (the fake
+    # pointers are never touched).
+    assert adj(10, FAKE, FAKE, 0.1, 0.01, 0, FAKE, FAKE, FAKE, o, None, check=False) == _lib.NBODY_OK
     assert adj(10, FAKE, FAKE, 0.1, 0.01, -1, FAKE, FAKE, None, o, None, check=False) == _lib.NBODY_EINVAL
     assert adj(10, FAKE, FAKE, 0.1, float("nan"), 2, FAKE, FAKE, None, o, None, check=False) == _lib.NBODY_EINVAL
     assert adj(10, FAKE, FAKE, 0.1, 0.01, 2, FAKE, None, None, o, None, check=False) == _lib.NBODY_EINVAL

@@ -24,12 +24,36 @@ def test_roofline_fields():
     pairs = 131072.0 ** 2
     r = bench.roofline("gravity", pairs, 5.0, "k", traffic=123)
     assert r["bound"] == "alu" and r["unit"] == "TFLOP/s" and r["traffic"] == 123
-    # 17 issue slots per pair at 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz, 20 flop per pair.
-    assert r["peak"] == pytest.approx(256 * 4 * 32 * 2.4e9 / 17 * 20 / 1e12)
+    # The published FP32 vector peak, 20 flop per gravity pair (the paper's count).
+    assert r["peak"] == 157.3
     assert r["achieved"] == pytest.approx(pairs * 20 / 5e-3 / 1e12)
-    assert r["frac"] == pytest.approx(r["achieved"] / r["peak"])
+    assert r["frac"] == pytest.approx(r["achieved"] / 157.3)
+    # The issue model beside it: 17 slots per pair at 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz.
+    im = r["issue_model"]
+    assert im["peak_pairs_per_s"] == pytest.approx(256 * 4 * 32 * 2.4e9 / 17)
+    assert im["frac"] == pytest.approx(pairs / 5e-3 / im["peak_pairs_per_s"])
     for kind, slots in (("jerk", 31), ("adjoint", 42)):
         assert bench.peak_pairs(kind) == pytest.approx(256 * 4 * 32 * 2.4e9 / slots)
+    f = bench.fractions("adjoint", pairs, 5.0)
+    assert f["frac"] == pytest.approx(pairs * 45 / 5e-3 / 157.3e12)
+
+
+def test_default_line_lists_every_configuration():
+    # The default run adds one compact entry per configuration of the workload set.
+    assert set(bench.CONFIG_WORKLOADS) == {"plummer_2048", "stress_1m", "clusters_2048",
+                                           "adjoint_16384"}
+    body = {"config": {"workload": "w", "step": "s"}, "ms_per_step": 1.0, "value": 2.0,
+            "roofline": bench.roofline("gravity", 1e6, 1.0, "k"),
+            "modes": {"comp": {"value": 2.0, "errors": {"acc_rel_rms": 1e-8}}},
+            "cpu_baseline": {"sample": "all"}, "error_split": {"none": {}}}
+    c = bench.compact(body)
+    assert c["pairs_per_s"] == 2.0 and c["roofline_frac"] == body["roofline"]["frac"]
+    assert c["issue_frac"] == body["roofline"]["issue_model"]["frac"]
+    assert c["modes"]["comp"] == {"errors": {"acc_rel_rms": 1e-8}} and "error_split" in c
+
+
+def test_cpu_model_is_reported():
+    assert isinstance(bench.cpu_model(), str) and bench.cpu_model()
 
 
 def test_committed_traffic_matches_the_current_sources():

@@ -4,6 +4,7 @@ import numpy as np
 import pytest
 import torch
 
+import bounds
 import oracle
 from paper_astro_ph_0703100_amd import api, ics
 from paper_astro_ph_0703100_amd.metrics import rel_errors
@@ -39,15 +40,13 @@ def oracle_batch(offsets, pos, m32, eps, systems=None):
     return out
 
 
-def pot_ok(pot, ref, m, eps, tol, adds=128):
-    """|phi - phi_ref| <= tol |phi_ref| + A u (m_i / eps + |phi_ref|).  The j == i term
-    m_i / eps sits in an FP32 partial before its exact removal; each of the at most A
-    FP32 additions that follow it rounds a partial no larger than m_i / eps + |phi_i|
-    (all potential terms share a sign).  A = 128, the longest FP32 block, for the FP64
-    and compensated modes; plain FP32 passes the segment length plus its segment sum."""
-    u = 2.0 ** -24
-    bound = tol * np.abs(ref) + adds * u * (m / eps + np.abs(ref))
-    return bool(np.all(np.abs(pot - ref) <= bound))
+def check_system_bounds(acc, pot, ra, rp, x, m32, eps, precision):
+    """Per-particle bounds of tests/bounds.py for one system (acc/pot: its rows)."""
+    n = x.shape[0]
+    absa, absp = oracle.force_abs_sampled(x, m32.astype(np.float64), eps, np.arange(n))
+    wa = bounds.check_acc(acc, ra, absa, precision, n)
+    wp = bounds.check_pot(pot, rp, absp, precision, n) if pot is not None else 0.0
+    return wa, wp
 
 
 SIZES = [0, 1, 2, 255, 256, 257, 1000, 3001, 1, 4097, 64, 0, 777]
@@ -77,8 +76,9 @@ def test_batched_force_matches_oracle_per_system(precision, ipl, jtile):
             continue
         ea, ep = rel_errors(acc[s:t], ra), rel_errors(pot[s:t], rp)
         assert ea["rel_rms"] <= tol, (k, t - s, ea)
-        adds = 128 if precision != "plain" else t - s + 1
-        assert pot_ok(pot[s:t], rp, m32[s:t], float(eps[k]), 10 * tol, adds), (k, t - s, ep)
+        assert ep["rel_rms"] <= tol, (k, t - s, ep)
+        check_system_bounds(acc[s:t], pot[s:t], ra, rp, x32[s:t].astype(np.float64), m32[s:t],
+                            float(eps[k]), precision)
     plan.close()
 
 
@@ -173,23 +173,29 @@ def test_clusters_2048_graph_leapfrog():
     v = torch.from_numpy(np.ascontiguousarray(b.vel.T)).to(DEV)
     m = torch.from_numpy(m32).to(DEV)
     e = torch.from_numpy(eps).to(DEV)
-    acc0, _ = plan.leapfrog(x, v, m, e, w.dt, 0)
+    acc0, pot0 = plan.leapfrog(x, v, m, e, w.dt, 0, with_pot=True)
     sizes = b.sizes
     rng = np.random.default_rng(w.seed + 1000)
     pick = sorted(set([int(np.argmin(sizes)), int(np.argmax(sizes))] +
                       list(rng.choice(b.nsys, size=14, replace=False))))
-    a0 = acc0.cpu().numpy().T
-    for k, (ra, _) in oracle_batch(b.offsets, b.pos, m32, eps, pick).items():
-        s, t = b.offsets[k], b.offsets[k + 1]
-        assert rel_errors(a0[s:t], ra)["rel_rms"] <= 1e-6, (k, t - s)
-    g = plan.graph(x, v, m, e, w.dt, w.steps, acc0)
+    assert min(sizes[k] for k in pick) < 300  # a smallest-cluster system is among them
+
+    def check(a, p, xs, label):
+        # Per system: acceleration and potential relative RMS <= 1e-6, and every
+        # particle inside the rounding bound (clusters of a few hundred particles have
+        # m_i / eps of the order of |phi_i|: no self term may leak into phi).
+        for k, (ra, rp) in oracle_batch(b.offsets, xs, m32, eps, pick).items():
+            s, t = b.offsets[k], b.offsets[k + 1]
+            ea, ep = rel_errors(a[s:t], ra), rel_errors(p[s:t], rp)
+            assert ea["rel_rms"] <= 1e-6, (label, k, t - s, ea)
+            assert ep["rel_rms"] <= 1e-6, (label, k, t - s, ep)
+            check_system_bounds(a[s:t], p[s:t], ra, rp, xs[s:t], m32[s:t], float(eps[k]), "comp")
+
+    check(acc0.cpu().numpy().T, pot0.cpu().numpy(), b.pos, "step 0")
+    pot = torch.empty_like(pot0)
+    g = plan.graph(x, v, m, e, w.dt, w.steps, acc0, pot)
     g.launch()
     torch.cuda.synchronize()
-    xs = x.cpu().numpy().T
-    a16 = acc0.cpu().numpy().T
-    for k, (ra, _) in oracle_batch(b.offsets, xs, m32, eps, pick).items():
-        s, t = b.offsets[k], b.offsets[k + 1]
-        er = rel_errors(a16[s:t], ra)
-        assert er["rel_rms"] <= 1e-6, (k, t - s, er)
+    check(acc0.cpu().numpy().T, pot.cpu().numpy(), x.cpu().numpy().T, "step 16")
     g.close()
     plan.close()

@@ -3,12 +3,14 @@
 The i-set and the j-set are different particles (or an i-range of one system against
 all of it); every pair counts, and the softening is uniform or given per i-particle.
 Tolerances as for the single-set path: compensated and FP64-reduced relative RMS
-<= 1e-6, plain FP32 <= 1e-5.
+<= 1e-6, plain FP32 <= 1e-5, and (uniform softening) the per-particle rounding bound
+of tests/bounds.py on every component.
 """
 import numpy as np
 import pytest
 import torch
 
+import bounds
 import oracle
 from paper_astro_ph_0703100_amd import _lib, api, ics
 from paper_astro_ph_0703100_amd.metrics import rel_errors
@@ -46,7 +48,10 @@ def test_separate_sets_uniform_eps(precision, ni, nj):
     acc, pot = run_ij(xi, xj, mj, eps, precision=precision)
     ra, rp = oracle.force_ij(as32(xj), as32(mj), as32(xi), eps)
     ea, ep = rel_errors(acc, ra), rel_errors(pot, rp)
-    print(precision, ni, nj, "acc", ea, "pot", ep)
+    absa, absp = oracle.force_abs(as32(xj), as32(mj), as32(xi), eps)
+    wa = bounds.check_acc(acc, ra, absa, precision, nj)
+    wp = bounds.check_pot(pot, rp, absp, precision, nj)
+    print(precision, ni, nj, "acc", ea, "pot", ep, "bound ratios %.2f %.2f" % (wa, wp))
     assert ea["rel_rms"] <= TOL[precision], ea
     assert ep["rel_rms"] <= TOL[precision], ep
 
@@ -132,7 +137,10 @@ def test_full_size_shard_sampled():
     idx = ics.sample_indices(ni, 512, seed=77)
     ra, rp = oracle.force_ij(as32(pos), as32(mass), as32(pos[idx]), eps)
     ea, ep = rel_errors(acc[idx], ra), rel_errors(pot[idx], rp)
-    print("shard acc", ea, "pot", ep)
+    absa, absp = oracle.force_abs(as32(pos), as32(mass), as32(pos[idx]), eps)
+    wa = bounds.check_acc(acc[idx], ra, absa, "comp", w.n)
+    wp = bounds.check_pot(pot[idx], rp, absp, "comp", w.n)
+    print("shard acc", ea, "pot", ep, "bound ratios %.2f %.2f" % (wa, wp))
     assert ea["rel_rms"] <= 1e-6, ea
     assert ep["rel_rms"] <= 1e-6, ep
 

@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 import torch
 
+import bounds
 import oracle
 from paper_astro_ph_0703100_amd import _lib, api, ics
 from paper_astro_ph_0703100_amd.metrics import rel_errors
@@ -52,13 +53,12 @@ def test_force(k):
     torch.cuda.synchronize()
     ra, rp = oracle.force_all(x, m, c["eps"])
     ea = rel_errors(acc.cpu().numpy().T, ra)
-    # The j == i potential term m_i / eps sits in an FP32 partial before its exact removal:
-    # each FP32 addition after it rounds a partial of at most m_i / eps + |phi_i| (all
-    # potential terms share a sign).  Those additions number fewer than one block,
-    # min(128, jtile), in the FP64 and compensated modes; plain FP32 adds the rest of the
-    # segment and the segment sum.
-    adds = min(128, c["jtile"]) if c["precision"] != "plain" else c["n"] + 1025
-    bound = 10 * TOL[c["precision"]] * np.abs(rp) + adds * U * (m / c["eps"] + np.abs(rp))
+    # Potential terms share a sign (sum |term| = |phi|): each is one rounded product
+    # after the rsq (C_POT u), followed by fewer than one block, min(128, jtile), of FP32
+    # additions in the FP64 and compensated modes; plain FP32 adds the rest of the
+    # segment and the segment sum.  The j == i pair adds nothing.
+    adds = min(128, c["jtile"]) - 1 if c["precision"] != "plain" else c["n"] + 1024
+    bound = (bounds.C_POT + adds) * U * np.abs(rp)
     assert ea["rel_rms"] <= TOL[c["precision"]], (c, ea)
     perr = np.abs(pot.cpu().numpy() - rp)
     worst = int(np.argmax(perr / bound))

@@ -104,3 +104,35 @@ def test_graph_creation_refuses_a_capturing_stream():
     g.replay()
     torch.cuda.synchronize()
     assert torch.all(ones == 2.0)
+
+
+def test_capture_without_a_workspace_is_refused():
+    # Recording a call that would use the library's own scratch cache is refused with
+    # NBODY_ECAPTURE (a later, larger call could reallocate that cache under the graph);
+    # nothing is enqueued and the caller's capture stays valid.
+    n, eps = 4096, 0.02
+    p, m = system(n, 85)
+    x64 = p.double().contiguous()
+    g_acc = torch.ones((3, n), dtype=torch.float64, device=DEV)
+    api.force(p, m, eps)  # the cache exists and is large enough: still refused
+    acc = torch.empty((3, n), dtype=torch.float64, device=DEV)
+    gx = torch.empty((3, n), dtype=torch.float64, device=DEV)
+    ones = torch.ones(16, device=DEV)
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        ones.add_(1.0)
+        st = _lib.nbody_force_ex(n, p.data_ptr(), m.data_ptr(), eps, acc.data_ptr(), None,
+                                 api.make_opts(), s.cuda_stream, check=False)
+        msg = _lib.nbody_last_error()
+        st64 = _lib.nbody_force_f64(n, x64.data_ptr(), m.data_ptr(), eps, acc.data_ptr(), None,
+                                    api.make_opts(), s.cuda_stream, check=False)
+        stv = _lib.nbody_force_vjp(n, p.data_ptr(), m.data_ptr(), eps, g_acc.data_ptr(), None,
+                                   gx.data_ptr(), None, api.make_opts(), s.cuda_stream,
+                                   check=False)
+    assert st == _lib.NBODY_ECAPTURE and "workspace" in msg, (st, msg)
+    assert st64 == _lib.NBODY_ECAPTURE and stv == _lib.NBODY_ECAPTURE
+    g.replay()
+    torch.cuda.synchronize()
+    assert torch.all(ones == 2.0)
