@@ -83,9 +83,27 @@ typedef struct nbody_opts {
     int32_t ipl;        /* i-particles per lane: 1, 2, 4, 8; 0 = tuned/default        */
     int32_t jtile;      /* j-particles per LDS tile: 64, 128, 256, 512; 0 = default   */
     int32_t nseg;       /* j-segments per i-tile (grid y), <= 1024; 0 = chosen from n */
+    int32_t jlanes;     /* lanes that share one i-particle's j-range (see below)       */
     void *workspace;    /* device scratch, or NULL for the library's per-device cache */
     size_t workspace_bytes;
 } nbody_opts;
+
+/* Launch shapes.  Two pair engines evaluate the same sums:
+ *   - the grid engine (jlanes = 1): a block of 256 lanes holds 256 * ipl i-particles
+ *     and walks one of nseg j-segments in LDS tiles of jtile records (64 to 512);
+ *     the segment partial sums go to scratch memory and a second kernel adds them
+ *     per particle in FP64 (the paper's i-parallel FORCE-LOOP, Sec. 2.2);
+ *   - the split engine (jlanes = 8, 16, 32 or 64; ipl = 1 or 2; jtile = 256, 512 or
+ *     1024, at most 512 for the adjoint; nseg must be 0): for systems too small to
+ *     fill the chip with whole i-tiles, the j-range of each i-particle is split over
+ *     jlanes lanes of one wavefront, whose partial sums are added across the lanes
+ *     in FP64 (PLAIN: FP32) by DPP / permlane moves in a fixed order.  One launch, no
+ *     scratch for partial sums.  Available for nbody_force, nbody_force_ex,
+ *     nbody_force_f64, the leapfrog, nbody_force_vjp(_f64) and the leapfrog adjoint,
+ *     not with NBODY_CENTRE_TILE (which uses the grid engine's i-tiles).
+ * jlanes = 0 with ipl, jtile and nseg all 0 takes the shape from the tuning table
+ * (either engine); jlanes = 0 with any of them set selects the grid engine.  Results
+ * are bitwise reproducible for a given shape; different shapes round differently. */
 
 /* Fills *opts with the defaults (NBODY_COMP, NBODY_CENTRE_SYSTEM, self excluded,
  * tile shape from the tuning table, library workspace). */
@@ -367,15 +385,18 @@ NBODY_API nbody_status nbody_graph_create_leapfrog_batched(const nbody_plan *pla
  * up per kernel, precision mode and size bucket floor(log2 n) (batched: mean system
  * size); entries not set use built-in defaults; explicit opts fields override both.
  * The autotuner (tune.py) measures shapes and writes the JSON file these functions
- * read and write.  nseg = 0 lets the library choose the j-split from n.
+ * read and write.  nseg = 0 lets the library choose the j-split from n.  The built-in
+ * defaults use the split engine for the force below 2^13 particles.
  * ---------------------------------------------------------------------------- */
 #define NBODY_KERNEL_FORCE 0
 #define NBODY_KERNEL_VJP 1
 #define NBODY_KERNEL_BATCHED 2
 #define NBODY_KERNEL_JERK 3
 NBODY_API nbody_status nbody_tune_set(int32_t kernel, int32_t precision, int64_t n, int32_t ipl,
-                                      int32_t jtile, int32_t nseg);
-/* shape[0..3) = ipl, jtile, nseg in effect for (kernel, precision, n). */
+                                      int32_t jtile, int32_t nseg, int32_t jlanes);
+/* shape[0..4) = ipl, jtile, nseg, jlanes in effect for (kernel, precision, n)
+ * (jlanes 1: grid engine; 8 to 64: split engine, only for NBODY_KERNEL_FORCE and
+ * NBODY_KERNEL_VJP). */
 NBODY_API nbody_status nbody_tune_get(int32_t kernel, int32_t precision, int64_t n,
                                       int32_t *shape);
 NBODY_API nbody_status nbody_tune_load(const char *path);

@@ -115,10 +115,40 @@ nbody_status get_workspace(const nbody_opts &o, size_t need, hipStream_t s, void
 // Launch shape for ni i-particles against nj j-particles: explicit options first, then
 // the tuning table (its j-split only when the two sets have the same size, the shape it
 // was measured on), then a default that gives every compute unit several blocks.
+// split_ok: the caller has a split-engine kernel for this evaluation (single-set force
+// or adjoint without per-i-tile centres); otherwise the grid engine is used.
 nbody_status choose_cfg_ij(int kernel, int64_t ni, int64_t nj, int precision, const nbody_opts &o,
-                           TileCfg *cfg) {
+                           TileCfg *cfg, bool split_ok) {
     TileCfg c;
-    TuneEntry t = tuned_shape(kernel, precision, nj);
+    if (o.jlanes < 0) return set_error(NBODY_EINVAL, "jlanes must be >= 0");
+    if (o.jlanes > 1 && !split_ok)
+        return set_error(NBODY_EUNSUPPORTED,
+                         "jlanes > 1 (split engine) is available for the single-set force and "
+                         "adjoint without per-i-tile centres only");
+    const bool explicit_shape = o.ipl || o.jtile || o.nseg;
+    TuneEntry t = tuned_shape(kernel, precision, nj, split_ok);
+    const int jl = o.jlanes ? o.jlanes : (explicit_shape ? 1 : t.jl);
+    if (jl > 1) {
+        // Split engine: one launch of ceil(ni / i-per-block) blocks, no j-segments.
+        const bool from_table = t.jl > 1;
+        TuneEntry e{o.ipl ? o.ipl : (from_table ? t.ipl : 1),
+                    o.jtile ? o.jtile : (from_table ? t.jt : 512), o.nseg, jl};
+        if (!valid_shape(kernel, e))
+            return set_error(NBODY_EINVAL,
+                             "split-engine shape needs jlanes in {8, 16, 32, 64}, ipl in {1, 2}, "
+                             "jtile in {256, 512, 1024} (adjoint: 256, 512) and nseg = 0");
+        c.ipl = e.ipl;
+        c.jt = e.jt;
+        c.jl = jl;
+        const int64_t per_block = (int64_t)4 * (64 / jl) * c.ipl;
+        c.itiles = (int)((ni + per_block - 1) / per_block);
+        c.nseg = 1;
+        c.seg_len = 0;
+        c.npad = 0;
+        *cfg = c;
+        return NBODY_OK;
+    }
+    if (t.jl > 1) t = TuneEntry{1, 256, 0, 1};  // the table's split shape does not apply
     c.ipl = o.ipl ? o.ipl : t.ipl;
     c.jt = o.jtile ? o.jtile : t.jt;
     if (!(c.ipl == 1 || c.ipl == 2 || c.ipl == 4 || c.ipl == 8))
@@ -152,11 +182,13 @@ nbody_status choose_cfg_ij(int kernel, int64_t ni, int64_t nj, int precision, co
     return NBODY_OK;
 }
 
-nbody_status choose_cfg(int kernel, int64_t n, int precision, const nbody_opts &o, TileCfg *cfg) {
-    return choose_cfg_ij(kernel, n, n, precision, o, cfg);
+nbody_status choose_cfg(int kernel, int64_t n, int precision, const nbody_opts &o, TileCfg *cfg,
+                        bool split_ok) {
+    return choose_cfg_ij(kernel, n, n, precision, o, cfg, split_ok);
 }
 
 size_t partial_bytes(const TileCfg &c, int precision) {
+    if (c.jl > 1) return 0;  // the split engine keeps its partial sums in registers
     return align_up((size_t)c.nseg * partial_words(precision) * (size_t)c.npad * 4, 256);
 }
 
@@ -214,10 +246,11 @@ nbody_status force_f32_core(int64_t n, const float *pos, const float *mass, floa
                             double *kick_v, double kick_h, hipStream_t s) {
     const float e2 = eps * eps;
     PairArgs pa{pos, pos + n, pos + 2 * n, mass, (int)n, cfg.seg_len, e2, ws, cfg.npad};
-    nbody_status st = launch_pair(cfg, o.precision, pot != nullptr, pa, s);
-    if (st) return st;
     FinalizeArgs fa{ws, cfg.nseg, cfg.npad, (int)n, mass, eps, o.self_pot, acc, pot, kick_v,
                     kick_h};
+    if (cfg.jl > 1) return launch_pair_split(cfg, o.precision, pot != nullptr, pa, fa, s);
+    nbody_status st = launch_pair(cfg, o.precision, pot != nullptr, pa, s);
+    if (st) return st;
     return launch_finalize(o.precision, fa, s);
 }
 
@@ -274,7 +307,8 @@ size_t nbody_workspace_size(int64_t n, const nbody_opts *opts) {
     if (opts) o = *opts;
     if (n <= 0) return 0;
     TileCfg c;
-    if (choose_cfg(KERNEL_FORCE, n, o.precision, o, &c) != NBODY_OK) return 0;
+    if (choose_cfg(KERNEL_FORCE, n, o.precision, o, &c, o.centre != NBODY_CENTRE_TILE) != NBODY_OK)
+        return 0;
     return f64_scratch_bytes(n, c, o.precision);
 }
 
@@ -287,7 +321,7 @@ nbody_status nbody_force_ex(int64_t n, const float *pos, const float *mass, floa
     if (n == 0) return NBODY_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
     TileCfg cfg;
-    if ((st = choose_cfg(KERNEL_FORCE, n, o.precision, o, &cfg))) return st;
+    if ((st = choose_cfg(KERNEL_FORCE, n, o.precision, o, &cfg, true))) return st;
     void *ws = nullptr;
     if ((st = get_workspace(o, partial_bytes(cfg, o.precision), s, &ws))) return st;
     return force_f32_core(n, pos, mass, eps, acc, pot, o, cfg, ws, nullptr, 0.0, s);
@@ -309,7 +343,7 @@ nbody_status nbody_force_f64(int64_t n, const double *pos64, const float *mass, 
     if (n == 0) return NBODY_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
     TileCfg cfg;
-    if ((st = choose_cfg(KERNEL_FORCE, n, o.precision, o, &cfg))) return st;
+    if ((st = choose_cfg(KERNEL_FORCE, n, o.precision, o, &cfg, o.centre != NBODY_CENTRE_TILE))) return st;
     void *ws = nullptr;
     if ((st = get_workspace(o, f64_scratch_bytes(n, cfg, o.precision), s, &ws))) return st;
     return force_f64_core(n, pos64, mass, eps, acc, pot, o, cfg,
@@ -342,7 +376,7 @@ nbody_status nbody_force_ij(int64_t ni, const float *pos_i, const float *eps_i, 
         return pot ? launch_fill_f64(ni, pot, 0.0, s) : NBODY_OK;
     }
     TileCfg cfg;
-    if ((st = choose_cfg_ij(KERNEL_FORCE, ni, nj, o.precision, o, &cfg))) return st;
+    if ((st = choose_cfg_ij(KERNEL_FORCE, ni, nj, o.precision, o, &cfg, false))) return st;
     void *ws = nullptr;
     if ((st = get_workspace(o, partial_bytes(cfg, o.precision), s, &ws))) return st;
     IJPairArgs a{pos_i, pos_i + ni, pos_i + 2 * ni, eps_i, pos_j, pos_j + nj, pos_j + 2 * nj,
@@ -356,7 +390,7 @@ size_t nbody_workspace_size_ij(int64_t ni, int64_t nj, const nbody_opts *opts) {
     nbody_opts o = resolve_opts(opts);
     if (ni <= 0 || nj <= 0) return 0;
     TileCfg c;
-    if (choose_cfg_ij(KERNEL_FORCE, ni, nj, o.precision, o, &c) != NBODY_OK) return 0;
+    if (choose_cfg_ij(KERNEL_FORCE, ni, nj, o.precision, o, &c, false) != NBODY_OK) return 0;
     return partial_bytes(c, o.precision);
 }
 

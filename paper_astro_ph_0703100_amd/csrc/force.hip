@@ -1,6 +1,7 @@
 // Force evaluation of one system: the gravity pipeline on the tile engine (grid
 // launch), the FP64 finalize, and the FP64-position pre-pass (centre, conversion).
 #include "gravity.h"
+#include "outputs.h"
 
 namespace nbody {
 namespace {
@@ -16,14 +17,8 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinalizeArgs a) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int c = blockIdx.y;
     if (i >= a.n) return;
-    double r = engine::sum_partial_output<4, MODE, BATCH>(a.part, a.nseg, (size_t)a.npad, i, c);
-    if (c == 3) {
-        if (a.include_self) r -= (double)a.m[i] / (double)a.eps;
-        a.pot[i] = r;
-        return;
-    }
-    a.acc[c * (size_t)a.n + i] = r;
-    if (a.kick_v) a.kick_v[c * (size_t)a.n + i] += a.kick_h * r;  // second kick, fused: v += h a
+    ForceOut::put(a, i, c, engine::sum_partial_output<4, MODE, BATCH>(a.part, a.nseg,
+                                                                       (size_t)a.npad, i, c));
 }
 
 // Two-stage fixed-order FP64 mean of the positions [3][n]: kCentreBlocks partial

@@ -47,6 +47,8 @@ struct TileCfg {
     int seg_len = 0; // j's per segment, a multiple of jt
     int itiles = 0;  // i-tiles (grid x)
     int npad = 0;    // itiles * kTPB * ipl
+    int jl = 1;      // lanes per i-particle's j-range: 1 = grid engine, 8..64 = split engine
+                     // (then itiles = blocks of 4 * (64 / jl) * ipl i's, nseg = 1)
 };
 
 // Arguments of the pair kernel (FP32 structure-of-arrays input).
@@ -241,10 +243,12 @@ inline bool misaligned(const T *p) {
 // Host helpers (api.cpp).
 bool stream_capturing(hipStream_t s);
 nbody_status get_workspace(const nbody_opts &o, size_t need, hipStream_t s, void **out);
-nbody_status choose_cfg(int kernel, int64_t n, int precision, const nbody_opts &o, TileCfg *cfg);
+// split_ok: the caller has a split-engine kernel for this evaluation.
+nbody_status choose_cfg(int kernel, int64_t n, int precision, const nbody_opts &o, TileCfg *cfg,
+                        bool split_ok);
 // The same for ni i-particles against nj j-particles (nj >= 1).
 nbody_status choose_cfg_ij(int kernel, int64_t ni, int64_t nj, int precision, const nbody_opts &o,
-                           TileCfg *cfg);
+                           TileCfg *cfg, bool split_ok);
 size_t partial_bytes(const TileCfg &c, int precision);
 size_t align_up(size_t v, size_t a);
 nbody_status check_common(int64_t n, const void *pos, const void *mass, float eps,
@@ -294,6 +298,12 @@ const DeviceInfo &device_info();
 nbody_status launch_pair(const TileCfg &cfg, int precision, bool with_pot, const PairArgs &a,
                          hipStream_t s);
 nbody_status launch_finalize(int precision, const FinalizeArgs &a, hipStream_t s);
+// Split engine (cfg.jl > 1): pair sums and outputs in one launch (force_split.hip,
+// vjp_split.hip); the finalize arguments say what is stored.
+nbody_status launch_pair_split(const TileCfg &cfg, int precision, bool with_pot,
+                               const PairArgs &a, const FinalizeArgs &f, hipStream_t s);
+nbody_status launch_vjp_split(const TileCfg &cfg, int precision, const VjpArgs &a, bool with_mass,
+                              const VjpFinalizeArgs &f, hipStream_t s);
 nbody_status launch_pair_ij(const TileCfg &cfg, int precision, bool with_pot, const IJPairArgs &a,
                             hipStream_t s);
 // fp32(x - c) with c the FP64 mean of all positions (two kernels: block partial sums,

@@ -2,10 +2,12 @@
 //
 // File format (written by nbody_tune_save and by tune.py):
 //   {"version": 1, "arch": "gfx950", "entries": [
-//     {"kernel": 0, "precision": 2, "bucket": 17, "ipl": 4, "jtile": 256, "nseg": 16}, ...]}
+//     {"kernel": 0, "precision": 2, "bucket": 17, "ipl": 4, "jtile": 256, "nseg": 16,
+//      "jlanes": 1}, ...]}
 // kernel: 0 force, 1 adjoint, 2 batched, 3 force-jerk; precision: 0 plain, 1 FP64-reduced,
 // 2 compensated; bucket: floor(log2 n) of the particle count (batched: mean system
-// size).  Unknown keys are ignored.
+// size); jlanes (1 if absent) selects the grid (1) or split (8..64) engine.  Unknown
+// keys are ignored.
 #include "tuning.h"
 
 #include <cctype>
@@ -25,24 +27,36 @@ std::mutex g_mu;
 bool g_set[KERNEL_COUNT][3][kBuckets];
 TuneEntry g_tab[KERNEL_COUNT][3][kBuckets];
 
-TuneEntry builtin(int kernel, int64_t n) {
+TuneEntry builtin(int kernel, int64_t n, bool split_ok) {
     // Measured on MI355X (tune.py): one i-particle per lane (37 VGPRs, 8 waves per
     // SIMD) and many j-segments beat wider i-tiles for every kernel and size tried;
-    // the j-split itself is chosen from n (nseg = 0).
-    (void)n;
+    // the j-split itself is chosen from n (nseg = 0).  Below 2^13 particles the force's
+    // single-launch split engine is faster (N = 2048: 7.0 against 10.2 us per
+    // evaluation; N = 4096: 10.8 against 12.7 us); from 2^13 on the grid engine is.
+    if (kernel == KERNEL_FORCE && split_ok && n < (int64_t(1) << 13))
+        return n < (int64_t(1) << 12) ? TuneEntry{1, 512, 0, 64} : TuneEntry{1, 1024, 0, 32};
     if (kernel == KERNEL_BATCHED) return {1, 64, 0};
     return {1, 256, 0};
 }
 
 bool valid_entry(int kernel, int precision, int bucket, const TuneEntry &e) {
     return kernel >= 0 && kernel < KERNEL_COUNT && precision >= 0 && precision <= 2 &&
-           bucket >= 0 && bucket < kBuckets &&
-           (e.ipl == 1 || e.ipl == 2 || e.ipl == 4 || e.ipl == 8) &&
-           (e.jt == 64 || e.jt == 128 || e.jt == 256 || e.jt == 512) && e.nseg >= 0 &&
-           e.nseg <= kMaxSeg;
+           bucket >= 0 && bucket < kBuckets && valid_shape(kernel, e);
 }
 
 }  // namespace
+
+bool valid_shape(int kernel, const TuneEntry &e) {
+    if (e.jl == 1)
+        return (e.ipl == 1 || e.ipl == 2 || e.ipl == 4 || e.ipl == 8) &&
+               (e.jt == 64 || e.jt == 128 || e.jt == 256 || e.jt == 512) && e.nseg >= 0 &&
+               e.nseg <= kMaxSeg;
+    // Split engine: force and adjoint only; the adjoint's 32-byte j-records cap the
+    // double-buffered tile at 512 records (32 KB of LDS).
+    if (kernel != KERNEL_FORCE && kernel != KERNEL_VJP) return false;
+    return (e.jl == 8 || e.jl == 16 || e.jl == 32 || e.jl == 64) && (e.ipl == 1 || e.ipl == 2) &&
+           (e.jt == 256 || e.jt == 512 || (e.jt == 1024 && kernel == KERNEL_FORCE)) && e.nseg == 0;
+}
 
 int size_bucket(int64_t n) {
     int b = 0;
@@ -50,12 +64,14 @@ int size_bucket(int64_t n) {
     return b;
 }
 
-TuneEntry tuned_shape(int kernel, int precision, int64_t n) {
-    if (kernel < 0 || kernel >= KERNEL_COUNT || precision < 0 || precision > 2) return builtin(0, n);
+TuneEntry tuned_shape(int kernel, int precision, int64_t n, bool split_ok) {
+    if (kernel < 0 || kernel >= KERNEL_COUNT || precision < 0 || precision > 2)
+        return builtin(0, n, false);
     std::lock_guard<std::mutex> lk(g_mu);
     const int b = size_bucket(n);
-    if (g_set[kernel][precision][b]) return g_tab[kernel][precision][b];
-    return builtin(kernel, n);
+    if (g_set[kernel][precision][b] && (split_ok || g_tab[kernel][precision][b].jl == 1))
+        return g_tab[kernel][precision][b];
+    return builtin(kernel, n, split_ok);
 }
 
 void set_tuned_shape(int kernel, int precision, int64_t n, const TuneEntry &e) {
@@ -73,9 +89,9 @@ using namespace nbody;
 extern "C" {
 
 nbody_status nbody_tune_set(int32_t kernel, int32_t precision, int64_t n, int32_t ipl,
-                            int32_t jtile, int32_t nseg) {
+                            int32_t jtile, int32_t nseg, int32_t jlanes) {
     clear_error();
-    const TuneEntry e{ipl, jtile, nseg};
+    const TuneEntry e{ipl, jtile, nseg, jlanes};
     if (n < 1 || !valid_entry(kernel, precision, size_bucket(n), e))
         return set_error(NBODY_EINVAL, "invalid tuning entry");
     set_tuned_shape(kernel, precision, n, e);
@@ -86,10 +102,11 @@ nbody_status nbody_tune_get(int32_t kernel, int32_t precision, int64_t n, int32_
     clear_error();
     if (!shape || kernel < 0 || kernel >= KERNEL_COUNT || precision < 0 || precision > 2 || n < 1)
         return set_error(NBODY_EINVAL, "invalid tuning query");
-    const TuneEntry e = tuned_shape(kernel, precision, n);
+    const TuneEntry e = tuned_shape(kernel, precision, n, true);
     shape[0] = e.ipl;
     shape[1] = e.jt;
     shape[2] = e.nseg;
+    shape[3] = e.jl;
     return NBODY_OK;
 }
 
@@ -115,8 +132,8 @@ nbody_status nbody_tune_save(const char *path) {
                     if (g_set[k][p][b]) {
                         const TuneEntry &e = g_tab[k][p][b];
                         std::fprintf(f, "%s\n  {\"kernel\": %d, \"precision\": %d, \"bucket\": %d, "
-                                        "\"ipl\": %d, \"jtile\": %d, \"nseg\": %d}",
-                                     first ? "" : ",", k, p, b, e.ipl, e.jt, e.nseg);
+                                        "\"ipl\": %d, \"jtile\": %d, \"nseg\": %d, \"jlanes\": %d}",
+                                     first ? "" : ",", k, p, b, e.ipl, e.jt, e.nseg, e.jl);
                         first = false;
                     }
     }
@@ -153,16 +170,17 @@ nbody_status nbody_tune_load(const char *path) {
         if (ob == std::string::npos || ob > end) break;
         const size_t cb = text.find('}', ob);
         if (cb == std::string::npos) return set_error(NBODY_EINVAL, "malformed tuning entry");
-        int v[6] = {-1, -1, -1, -1, -1, -1};
-        const char *keys[6] = {"\"kernel\"", "\"precision\"", "\"bucket\"", "\"ipl\"", "\"jtile\"", "\"nseg\""};
-        for (int q = 0; q < 6; ++q) {
+        int v[7] = {-1, -1, -1, -1, -1, -1, 1};  // jlanes absent: grid engine
+        const char *keys[7] = {"\"kernel\"", "\"precision\"", "\"bucket\"", "\"ipl\"",
+                               "\"jtile\"",  "\"nseg\"",      "\"jlanes\""};
+        for (int q = 0; q < 7; ++q) {
             const size_t kp = text.find(keys[q], ob);
             if (kp == std::string::npos || kp > cb) continue;
             const size_t colon = text.find(':', kp);
             if (colon == std::string::npos || colon > cb) continue;
             v[q] = std::atoi(text.c_str() + colon + 1);
         }
-        const TuneEntry e{v[3], v[4], v[5]};
+        const TuneEntry e{v[3], v[4], v[5], v[6]};
         if (!valid_entry(v[0], v[1], v[2], e))
             return set_error(NBODY_EINVAL, "invalid tuning entry in " + std::string(path));
         entries.push_back({v[0], v[1], v[2], e});

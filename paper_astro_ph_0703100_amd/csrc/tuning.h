@@ -9,16 +9,22 @@ namespace nbody {
 enum TuneKernel { KERNEL_FORCE = 0, KERNEL_VJP = 1, KERNEL_BATCHED = 2, KERNEL_JERK = 3, KERNEL_COUNT = 4 };
 
 struct TuneEntry {
-    int ipl;   // i-particles per lane
-    int jt;    // j-tile
-    int nseg;  // j-segments, 0 = chosen from n
+    int ipl;     // i-particles per lane
+    int jt;      // j-tile
+    int nseg;    // j-segments, 0 = chosen from n (grid engine)
+    int jl = 1;  // lanes per i-particle's j-range: 1 = grid engine, 8..64 = split engine
 };
+
+// True if (ipl, jt, nseg, jl) is a shape the library has kernels for (kernel: TuneKernel).
+bool valid_shape(int kernel, const TuneEntry &e);
 
 // floor(log2 n) (0 for n < 2): the size bucket of the table.
 int size_bucket(int64_t n);
 
 // Shape for a kernel, precision mode and problem size (size bucket = floor(log2 n)).
-TuneEntry tuned_shape(int kernel, int precision, int64_t n);
+// Without split_ok (the caller has no split-engine kernel) a split entry of the table
+// is passed over for the built-in grid-engine shape.
+TuneEntry tuned_shape(int kernel, int precision, int64_t n, bool split_ok);
 
 // Replace the entry for (kernel, precision, size bucket of n).
 void set_tuned_shape(int kernel, int precision, int64_t n, const TuneEntry &e);

@@ -1,6 +1,7 @@
 // Launch of the adjoint pipeline on FP32 positions and the FP64 finalize of its
 // partial sums.
 #include "adjoint_pipeline.h"
+#include "outputs.h"
 
 namespace nbody {
 namespace {
@@ -13,14 +14,8 @@ __global__ __launch_bounds__(256) void vjp_finalize_kernel(VjpFinalizeArgs a) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     const int c = blockIdx.y;
     if (k >= a.n) return;
-    const double r = engine::sum_partial_output<4, MODE, BATCH>(a.part, a.nseg, (size_t)a.npad, k, c);
-    if (c < 3) {
-        double *g = a.grad_pos + (size_t)c * a.n + k;
-        *g = a.accumulate ? *g + r : r;
-        return;
-    }
-    const double gm = -r;
-    a.grad_mass[k] = a.accumulate ? a.grad_mass[k] + gm : gm;
+    VjpOut::put(a, k, c, engine::sum_partial_output<4, MODE, BATCH>(a.part, a.nseg,
+                                                                      (size_t)a.npad, k, c));
 }
 
 }  // namespace

@@ -2,8 +2,11 @@
 
 For each workload it sweeps i-particles per lane (1, 2, 4, 8), j-tile (64 .. 512)
 and, for the single-system kernels (force, force-jerk, adjoint), the number of
-j-segments; times every shape with
-HIP events on the launch stream (median of ``reps`` after a warm-up call); and admits
+j-segments of the grid engine; for the force and the adjoint up to 2^15 particles
+also the split engine's shapes (lanes per i-particle 8 .. 64, i-particles per lane 1
+or 2, j-tile 256 .. 1024).  Every shape is timed with HIP events on the launch stream
+(median of ``reps`` runs of back-to-back calls, each run at least about a millisecond
+long, after a warm-up call); and admits
 a shape only if its result matches a reference computed on the same GPU with FP64
 reduction at the built-in shape (relative RMS <= 1e-6, plain FP32 <= 2e-5).  The
 fastest admitted shape is stored with ``nbody_tune_set`` and the table is written
@@ -27,22 +30,50 @@ from .metrics import rel_errors
 IPLS = (1, 2, 4, 8)
 JTILES = (64, 128, 256, 512)
 SEGS = (0, 4, 8, 10, 12, 16, 20, 24, 32, 40, 48, 64, 96, 128)
+# Split engine: (ipl, jlanes, jtile); the adjoint's 32-byte j-records stop at 512.
+SPLIT_MAX_N = 1 << 15
+SPLIT = [(ipl, jl, jt) for ipl in (1, 2) for jl in (8, 16, 32, 64) for jt in (256, 512, 1024)]
 GATE = {"comp": 1e-6, "fp64red": 1e-6, "plain": 2e-5}
 
 
+def shapes(n: int, kernel: str):
+    """Launch shapes to sweep for ``n`` particles: dicts of ipl, jtile, nseg, jlanes."""
+    out = []
+    for ipl in IPLS:
+        for jt in JTILES:
+            jtiles = (n + jt - 1) // jt
+            for nseg in SEGS:
+                if nseg <= jtiles:
+                    out.append({"ipl": ipl, "jtile": jt, "nseg": nseg, "jlanes": 1})
+    if kernel in ("force", "vjp") and n <= SPLIT_MAX_N:
+        for ipl, jl, jt in SPLIT:
+            if kernel == "vjp" and jt > 512:
+                continue
+            out.append({"ipl": ipl, "jtile": jt, "nseg": 0, "jlanes": jl})
+    return out
+
+
 def _time(call, reps: int) -> float:
-    """Median milliseconds of ``call`` (events on the current stream)."""
+    """Median milliseconds per call (events on the current stream around runs of
+    back-to-back calls, each run about a millisecond or longer)."""
     call()
     torch.cuda.synchronize()
-    times = []
     s = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(s)
+    call()
+    b.record(s)
+    b.synchronize()
+    inner = max(1, min(200, int(1.0 / max(a.elapsed_time(b), 1e-3))))
+    times = []
     for _ in range(reps):
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record(s)
-        call()
+        for _ in range(inner):
+            call()
         b.record(s)
         b.synchronize()
-        times.append(a.elapsed_time(b))
+        times.append(a.elapsed_time(b) / inner)
     return float(np.median(times))
 
 
@@ -62,28 +93,21 @@ def tune_force(n: int, seed: int, eps: float, precision: str, reps: int = 3, log
     pot = torch.empty(n, dtype=torch.float64, device=dev)
     best = None
     rows = []
-    for ipl in IPLS:
-        for jt in JTILES:
-            jtiles = (n + jt - 1) // jt
-            for nseg in SEGS:
-                if nseg > jtiles:
-                    continue
-                opts = api.make_opts(precision=precision, ipl=ipl, jtile=jt, nseg=nseg)
-                call = lambda: _lib.nbody_force_ex(n, p.data_ptr(), m.data_ptr(), eps,
-                                                   acc.data_ptr(), pot.data_ptr(), opts,
-                                                   api.stream_ptr())
-                ms = _time(call, reps)
-                ea = rel_errors(_host(acc).T, ref_a)["rel_rms"]
-                ep = rel_errors(_host(pot), ref_p)["rel_rms"]
-                ok = ea <= GATE[precision] and ep <= GATE[precision]
-                row = {"kernel": "force", "precision": precision, "n": n, "ipl": ipl,
-                       "jtile": jt, "nseg": nseg, "ms": ms, "acc_rel_rms": ea, "ok": ok,
-                       "pairs_per_s": n * n / (ms * 1e-3)}
-                rows.append(row)
-                if log:
-                    log(row)
-                if ok and (best is None or ms < best["ms"]):
-                    best = row
+    for sh in shapes(n, "force"):
+        opts = api.make_opts(precision=precision, **sh)
+        call = lambda: _lib.nbody_force_ex(n, p.data_ptr(), m.data_ptr(), eps, acc.data_ptr(),
+                                           pot.data_ptr(), opts, api.stream_ptr())
+        ms = _time(call, reps)
+        ea = rel_errors(_host(acc).T, ref_a)["rel_rms"]
+        ep = rel_errors(_host(pot), ref_p)["rel_rms"]
+        ok = ea <= GATE[precision] and ep <= GATE[precision]
+        row = dict({"kernel": "force", "precision": precision, "n": n}, **sh)
+        row.update({"ms": ms, "acc_rel_rms": ea, "ok": ok, "pairs_per_s": n * n / (ms * 1e-3)})
+        rows.append(row)
+        if log:
+            log(row)
+        if ok and (best is None or ms < best["ms"]):
+            best = row
     return best, rows
 
 
@@ -143,24 +167,17 @@ def tune_vjp(n: int, seed: int, eps: float, precision: str, reps: int = 3, log=N
     torch.cuda.synchronize()
     ref = _host(gx).T.copy()
     best, rows = None, []
-    for ipl in IPLS:
-        for jt in JTILES:
-            jtiles = (n + jt - 1) // jt
-            for nseg in SEGS:
-                if nseg > jtiles:
-                    continue
-                ms = _time(run(api.make_opts(precision=precision, ipl=ipl, jtile=jt, nseg=nseg)),
-                           reps)
-                e = rel_errors(_host(gx).T, ref)["normwise"]
-                ok = e <= 1e-6
-                row = {"kernel": "vjp", "precision": precision, "n": n, "ipl": ipl, "jtile": jt,
-                       "nseg": nseg, "ms": ms, "normwise": e, "ok": ok,
-                       "pairs_per_s": n * n / (ms * 1e-3)}
-                rows.append(row)
-                if log:
-                    log(row)
-                if ok and (best is None or ms < best["ms"]):
-                    best = row
+    for sh in shapes(n, "vjp"):
+        ms = _time(run(api.make_opts(precision=precision, **sh)), reps)
+        e = rel_errors(_host(gx).T, ref)["normwise"]
+        ok = e <= 1e-6
+        row = dict({"kernel": "vjp", "precision": precision, "n": n}, **sh)
+        row.update({"ms": ms, "normwise": e, "ok": ok, "pairs_per_s": n * n / (ms * 1e-3)})
+        rows.append(row)
+        if log:
+            log(row)
+        if ok and (best is None or ms < best["ms"]):
+            best = row
     return best, rows
 
 
@@ -229,7 +246,7 @@ def main(argv=None):
     for prec in ("comp", "plain", "fp64red"):
         jobs.append(("force", prec, lambda prec=prec: tune_force(w.n, w.seed, eps, prec, args.reps, log)))
     if not args.quick:
-        for n in (2048, 16384, 32768):
+        for n in (2048, 4096, 8192, 16384, 32768):
             jobs.append(("force", "comp", lambda n=n: tune_force(n, 10 + n, 0.01, "comp", args.reps, log)))
         jobs.append(("jerk", "comp", lambda: tune_jerk(w.n, w.seed, eps, "comp", args.reps, log)))
         wa = ics.WORKLOADS["adjoint_16384"]
@@ -247,12 +264,13 @@ def main(argv=None):
             print("tune: no shape passed the parity gate for %s/%s" % (kernel, prec), file=sys.stderr)
             continue
         _lib.nbody_tune_set(_lib.KERNELS[kernel], _lib.PRECISIONS[prec], best["n"], best["ipl"],
-                            best["jtile"], best["nseg"])
+                            best["jtile"], best["nseg"], best.get("jlanes", 1))
         default = [r for r in rows if r["ok"]]
-        print("tune: %-7s %-7s n=%-7d best ipl=%d jtile=%d nseg=%d  %.3f ms  %.3g pairs/s "
-              "(%d shapes, slowest admitted %.3f ms)"
-              % (kernel, prec, best["n"], best["ipl"], best["jtile"], best["nseg"], best["ms"],
-                 best["pairs_per_s"], len(rows), max(r["ms"] for r in default)), flush=True)
+        print("tune: %-7s %-7s n=%-7d best ipl=%d jtile=%d nseg=%d jlanes=%d  %.4f ms  %.3g "
+              "pairs/s (%d shapes, slowest admitted %.3f ms)"
+              % (kernel, prec, best["n"], best["ipl"], best["jtile"], best["nseg"],
+                 best.get("jlanes", 1), best["ms"], best["pairs_per_s"], len(rows),
+                 max(r["ms"] for r in default)), flush=True)
         summary.append(best)
     _lib.nbody_tune_save(args.out)
     print("tune: wrote %s" % args.out, flush=True)

@@ -41,9 +41,11 @@ def test_opts_layout_and_defaults():
     o = _lib.nbody_opts_default()
     assert o.precision == _lib.NBODY_COMP
     assert o.centre == _lib.NBODY_CENTRE_SYSTEM
-    assert o.self_pot == 0 and o.ipl == 0 and o.jtile == 0 and o.nseg == 0
+    assert o.self_pot == 0 and o.ipl == 0 and o.jtile == 0 and o.nseg == 0 and o.jlanes == 0
     assert not o.workspace and o.workspace_bytes == 0
-    assert ctypes.sizeof(_lib.nbody_opts) == 40
+    # seven int32 fields, padding to 8, a pointer and a size_t (the header's layout)
+    assert ctypes.sizeof(_lib.nbody_opts) == 48
+    assert _lib.nbody_opts.workspace.offset == 32
     assert _lib.nbody_version().startswith("nbody")
 
 
@@ -157,12 +159,42 @@ def test_force_ij_empty_i_set_is_a_no_op():
 @pytest.mark.parametrize("field,value", [
     ("precision", 3), ("precision", -1), ("self_pot", 2), ("centre", 5),
     ("ipl", 3), ("jtile", 100), ("nseg", -2), ("nseg", 100000),
+    ("jlanes", -1), ("jlanes", 3), ("jlanes", 4), ("jlanes", 128),
 ])
 def test_force_ex_rejects_bad_options(field, value):
     o = _lib.nbody_opts_default()
     setattr(o, field, value)
     st = _lib.nbody_force_ex(4096, FAKE, FAKE, 0.1, FAKE, FAKE, o, None, check=False)
     assert st == _lib.NBODY_EINVAL, (field, value, _lib.nbody_last_error())
+
+
+@pytest.mark.parametrize("ipl,jtile,nseg,jlanes", [
+    (4, 512, 0, 16), (1, 64, 0, 16), (1, 2048, 0, 16), (1, 512, 3, 16)])
+def test_force_ex_rejects_bad_split_shapes(ipl, jtile, nseg, jlanes):
+    o = _lib.nbody_opts_default()
+    o.ipl, o.jtile, o.nseg, o.jlanes = ipl, jtile, nseg, jlanes
+    st = _lib.nbody_force_ex(4096, FAKE, FAKE, 0.1, FAKE, FAKE, o, None, check=False)
+    assert st == _lib.NBODY_EINVAL, _lib.nbody_last_error()
+
+
+def test_split_engine_refused_where_not_built():
+    """jlanes > 1 on entry points without split-engine kernels: NBODY_EUNSUPPORTED before
+    anything is enqueued (separate sets, force-jerk, tile centres, batched plans)."""
+    o = _lib.nbody_opts_default()
+    o.jlanes = 16
+    assert _lib.nbody_force_ij(10, FAKE, None, 10, FAKE, FAKE, 0.1, FAKE, None, o, None,
+                               check=False) == _lib.NBODY_EUNSUPPORTED
+    assert _lib.nbody_force_jerk(10, FAKE, FAKE, FAKE, 0.1, FAKE, FAKE, None, o, None,
+                                 check=False) == _lib.NBODY_EUNSUPPORTED
+    o.centre = _lib.NBODY_CENTRE_TILE
+    assert _lib.nbody_force_f64(10, FAKE, FAKE, 0.1, FAKE, None, o, None,
+                                check=False) == _lib.NBODY_EUNSUPPORTED
+    o.centre = _lib.NBODY_CENTRE_SYSTEM
+    arr = (ctypes.c_int64 * 3)(0, 5, 9)
+    h = ctypes.c_void_p()
+    assert _lib.load().nbody_plan_create_batched(2, arr, ctypes.byref(o), ctypes.byref(h)) == \
+        _lib.NBODY_EUNSUPPORTED
+    assert h.value is None
 
 
 def test_force_f64_rejects_misaligned_and_bad_args():
@@ -200,11 +232,12 @@ def test_vjp_and_adjoint_workspace_sizes():
         v = _lib.nbody_workspace_size_vjp(n, o)
         a = _lib.nbody_workspace_size_adjoint(n, o)
         assert v > 0 and a == v + 3 * 8 * n
-    # The adjoint's own launch shape: an explicit j-split changes the VJP size only.
-    o.nseg = 8
-    assert _lib.nbody_workspace_size_vjp(16384, o) < _lib.nbody_workspace_size_vjp(
-        16384, _lib.nbody_opts_default())
-    o.nseg = 0
+    # The adjoint's own launch shape: the grid engine's j-split sets the VJP size.
+    o.jlanes, o.nseg = 1, 8
+    few = _lib.nbody_workspace_size_vjp(16384, o)
+    o.nseg = 64
+    assert few < _lib.nbody_workspace_size_vjp(16384, o)
+    o.jlanes, o.nseg = 0, 0
     o.ipl = 3
     assert _lib.nbody_workspace_size_vjp(16384, o) == 0
 
@@ -322,33 +355,60 @@ def test_tuning_table_roundtrip(tmp_path):
     assert base[0] in (1, 2, 4, 8) and base[1] in (64, 128, 256, 512)
     _lib.nbody_tune_set(_lib.NBODY_KERNEL_FORCE, _lib.NBODY_COMP, 131072, 8, 512, 12)
     _lib.nbody_tune_set(_lib.NBODY_KERNEL_VJP, _lib.NBODY_PLAIN, 5000, 1, 64, 3)
-    assert _lib.nbody_tune_get(_lib.NBODY_KERNEL_FORCE, _lib.NBODY_COMP, 131072) == (8, 512, 12)
+    _lib.nbody_tune_set(_lib.NBODY_KERNEL_FORCE, _lib.NBODY_FP64RED, 3000, 2, 1024, 0, 32)
+    assert _lib.nbody_tune_get(_lib.NBODY_KERNEL_FORCE, _lib.NBODY_COMP, 131072) == (8, 512, 12, 1)
     # Same size bucket (floor(log2 n) = 17), other precision untouched.
-    assert _lib.nbody_tune_get(_lib.NBODY_KERNEL_FORCE, _lib.NBODY_COMP, 200000) == (8, 512, 12)
+    assert _lib.nbody_tune_get(_lib.NBODY_KERNEL_FORCE, _lib.NBODY_COMP, 200000) == (8, 512, 12, 1)
     assert _lib.nbody_tune_get(_lib.NBODY_KERNEL_FORCE, _lib.NBODY_PLAIN, 131072) == base
     path = tmp_path / "t.json"
     _lib.nbody_tune_save(path)
+    assert '"jlanes": 32' in path.read_text()
     _lib.nbody_tune_reset()
     assert _lib.nbody_tune_get(_lib.NBODY_KERNEL_FORCE, _lib.NBODY_COMP, 131072) == base
     _lib.nbody_tune_load(path)
-    assert _lib.nbody_tune_get(_lib.NBODY_KERNEL_FORCE, _lib.NBODY_COMP, 131072) == (8, 512, 12)
-    assert _lib.nbody_tune_get(_lib.NBODY_KERNEL_VJP, _lib.NBODY_PLAIN, 4096) == (1, 64, 3)
+    assert _lib.nbody_tune_get(_lib.NBODY_KERNEL_FORCE, _lib.NBODY_COMP, 131072) == (8, 512, 12, 1)
+    assert _lib.nbody_tune_get(_lib.NBODY_KERNEL_VJP, _lib.NBODY_PLAIN, 4096) == (1, 64, 3, 1)
+    assert _lib.nbody_tune_get(_lib.NBODY_KERNEL_FORCE, _lib.NBODY_FP64RED, 2048) == (2, 1024, 0, 32)
+    # A file without "jlanes" keys (the earlier format) loads as grid-engine shapes.
+    old = tmp_path / "old.json"
+    old.write_text('{"entries": [{"kernel": 0, "precision": 2, "bucket": 12, "ipl": 2, '
+                   '"jtile": 128, "nseg": 5}]}')
+    _lib.nbody_tune_load(old)
+    assert _lib.nbody_tune_get(_lib.NBODY_KERNEL_FORCE, _lib.NBODY_COMP, 4096) == (2, 128, 5, 1)
     _lib.nbody_tune_reset()
     # Workspace sizing follows the table.
     o = _lib.nbody_opts_default()
     w0 = _lib.nbody_workspace_size(131072, o)
     _lib.nbody_tune_set(_lib.NBODY_KERNEL_FORCE, _lib.NBODY_COMP, 131072, 4, 256, 32)
     assert _lib.nbody_workspace_size(131072, o) > w0
+    # A split-engine shape keeps its partial sums in registers: the FP64-position path
+    # then needs only the FP32 positions and the centre partials.
+    _lib.nbody_tune_set(_lib.NBODY_KERNEL_FORCE, _lib.NBODY_COMP, 4096, 1, 512, 0, 16)
+    ws = _lib.nbody_workspace_size(4096, o)
+    assert 4096 * 12 <= ws <= 4096 * 12 + 16384
+    o.centre = _lib.NBODY_CENTRE_TILE  # the tile-centre path runs the grid engine
+    assert _lib.nbody_workspace_size(4096, o) > ws
     _lib.nbody_tune_reset()
     if os.path.exists(_lib.TUNING_PATH):
         _lib.nbody_tune_load(_lib.TUNING_PATH)
 
 
 def test_tuning_rejects_bad_entries(tmp_path):
-    assert _lib.load().nbody_tune_set(0, 2, 1000, 3, 256, 0) == _lib.NBODY_EINVAL
-    assert _lib.load().nbody_tune_set(0, 2, 1000, 4, 100, 0) == _lib.NBODY_EINVAL
-    assert _lib.load().nbody_tune_set(5, 2, 1000, 4, 256, 0) == _lib.NBODY_EINVAL
-    assert _lib.load().nbody_tune_set(0, 2, 0, 4, 256, 0) == _lib.NBODY_EINVAL
+    bad = _lib.load().nbody_tune_set
+    assert bad(0, 2, 1000, 3, 256, 0, 1) == _lib.NBODY_EINVAL
+    assert bad(0, 2, 1000, 4, 100, 0, 1) == _lib.NBODY_EINVAL
+    assert bad(5, 2, 1000, 4, 256, 0, 1) == _lib.NBODY_EINVAL
+    assert bad(0, 2, 0, 4, 256, 0, 1) == _lib.NBODY_EINVAL
+    # split-engine entries: jlanes 8..64, ipl 1 or 2, jtile 256..1024 (adjoint <= 512),
+    # nseg 0, force and adjoint only
+    assert bad(0, 2, 1000, 1, 512, 0, 4) == _lib.NBODY_EINVAL
+    assert bad(0, 2, 1000, 4, 512, 0, 16) == _lib.NBODY_EINVAL
+    assert bad(0, 2, 1000, 1, 128, 0, 16) == _lib.NBODY_EINVAL
+    assert bad(0, 2, 1000, 1, 512, 8, 16) == _lib.NBODY_EINVAL
+    assert bad(1, 2, 1000, 1, 1024, 0, 16) == _lib.NBODY_EINVAL
+    assert bad(2, 2, 1000, 1, 512, 0, 16) == _lib.NBODY_EINVAL
+    assert bad(3, 2, 1000, 1, 512, 0, 16) == _lib.NBODY_EINVAL
+    assert bad(0, 2, 1000, 1, 512, 0, 0) == _lib.NBODY_EINVAL
     bad = tmp_path / "bad.json"
     bad.write_text('{"entries": [{"kernel": 0, "precision": 2, "bucket": 17, "ipl": 3, '
                    '"jtile": 256, "nseg": 0}]}')
