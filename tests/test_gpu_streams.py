@@ -109,8 +109,10 @@ def test_graph_creation_refuses_a_capturing_stream():
 def test_capture_without_a_workspace_is_refused():
     # Recording a call that would use the library's own scratch cache is refused with
     # NBODY_ECAPTURE (a later, larger call could reallocate that cache under the graph);
-    # nothing is enqueued and the caller's capture stays valid.
+    # nothing is enqueued and the caller's capture stays valid.  (The grid engine keeps
+    # partial sums in scratch; the FP64-position paths need scratch with either engine.)
     n, eps = 4096, 0.02
+    grid = dict(jlanes=1)
     p, m = system(n, 85)
     x64 = p.double().contiguous()
     g_acc = torch.ones((3, n), dtype=torch.float64, device=DEV)
@@ -124,15 +126,42 @@ def test_capture_without_a_workspace_is_refused():
     with torch.cuda.graph(g, stream=s):
         ones.add_(1.0)
         st = _lib.nbody_force_ex(n, p.data_ptr(), m.data_ptr(), eps, acc.data_ptr(), None,
-                                 api.make_opts(), s.cuda_stream, check=False)
+                                 api.make_opts(**grid), s.cuda_stream, check=False)
         msg = _lib.nbody_last_error()
         st64 = _lib.nbody_force_f64(n, x64.data_ptr(), m.data_ptr(), eps, acc.data_ptr(), None,
                                     api.make_opts(), s.cuda_stream, check=False)
         stv = _lib.nbody_force_vjp(n, p.data_ptr(), m.data_ptr(), eps, g_acc.data_ptr(), None,
-                                   gx.data_ptr(), None, api.make_opts(), s.cuda_stream,
+                                   gx.data_ptr(), None, api.make_opts(**grid), s.cuda_stream,
                                    check=False)
     assert st == _lib.NBODY_ECAPTURE and "workspace" in msg, (st, msg)
     assert st64 == _lib.NBODY_ECAPTURE and stv == _lib.NBODY_ECAPTURE
     g.replay()
     torch.cuda.synchronize()
     assert torch.all(ones == 2.0)
+
+
+def test_split_engine_captures_without_a_workspace():
+    # The split engine on FP32 positions uses no scratch at all, so a capture needs no
+    # workspace; every replay (with eager work between them) matches the eager result.
+    n, eps = 3000, 0.02
+    p, m = system(n, 86)
+    shape = dict(ipl=1, jtile=512, jlanes=64)
+    ref_a, ref_p = api.force(p, m, eps, **shape)
+    acc = torch.empty((3, n), dtype=torch.float64, device=DEV)
+    pot = torch.empty(n, dtype=torch.float64, device=DEV)
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        st = _lib.nbody_force_ex(n, p.data_ptr(), m.data_ptr(), eps, acc.data_ptr(),
+                                 pot.data_ptr(), api.make_opts(**shape), s.cuda_stream,
+                                 check=False)
+    assert st == _lib.NBODY_OK, _lib.nbody_last_error()
+    for _ in range(3):
+        acc.zero_()
+        pot.zero_()
+        g.replay()
+        api.force(p, m, 2 * eps)  # unrelated eager work between replays
+        torch.cuda.synchronize()
+        assert torch.equal(acc, ref_a) and torch.equal(pot, ref_p)
+
