@@ -147,6 +147,26 @@ NBODY_API nbody_status nbody_force_f64(int64_t n, const double *pos64, const flo
                              double *acc, double *pot, const nbody_opts *opts, void *stream);
 
 /* ------------------------------------------------------------------------------
+ * As nbody_force_ex, for callers that cannot allocate device memory: code being
+ * captured into a HIP graph without a workspace of its own, tight serving loops,
+ * harnesses that forbid hipMalloc.  It calls no hipMalloc, hipFree or allocating
+ * library routine.  The grid engine's segment partial sums go to a static device
+ * array of NBODY_NOALLOC_SCRATCH_BYTES that every GPU the library runs on holds until
+ * the process ends; the split engine needs none.  If the partial sums of the chosen
+ * shape do not fit, fewer j-segments are used (unless opts->nseg is set); a size or
+ * shape whose partial sums exceed the array even then returns NBODY_EINVAL with the
+ * bytes it would need.  opts->workspace must be NULL.  All calls on one GPU share its
+ * array: calls that overlap in time on one GPU (several streams, several host
+ * threads) race and give wrong results; calls on one stream are ordered and safe.
+ * Nothing in the array needs clearing between calls (every partial sum is written
+ * before it is read).  Other arguments, results and errors as nbody_force_ex.
+ * ---------------------------------------------------------------------------- */
+#define NBODY_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20) /* 64 MiB per GPU */
+NBODY_API nbody_status nbody_force_noalloc(int64_t n, const float *pos, const float *mass,
+                                           float eps, double *acc, double *pot,
+                                           const nbody_opts *opts, void *stream);
+
+/* ------------------------------------------------------------------------------
  * Forces and potentials on one set of particles from another (the paper's library
  * call takes separate i- and j-arrays, Sec. 3.1; its driver keeps eps^2 per
  * i-particle, Appendix A).  Every (i, j) pair is summed: no pair is treated as a

@@ -79,6 +79,7 @@ SIGNATURES = {
     "nbody_force": (_I32, [_I64, _P, _P, _F, _P, _P, _P]),
     "nbody_force_ex": (_I32, [_I64, _P, _P, _F, _P, _P, _OPTS, _P]),
     "nbody_force_f64": (_I32, [_I64, _P, _P, _F, _P, _P, _OPTS, _P]),
+    "nbody_force_noalloc": (_I32, [_I64, _P, _P, _F, _P, _P, _OPTS, _P]),
     "nbody_force_ij": (_I32, [_I64, _P, _P, _I64, _P, _P, _F, _P, _P, _OPTS, _P]),
     "nbody_workspace_size_ij": (ctypes.c_size_t, [_I64, _I64, _OPTS]),
     "nbody_force_jerk": (_I32, [_I64, _P, _P, _P, _F, _P, _P, _P, _OPTS, _P]),
@@ -189,6 +190,15 @@ def nbody_force_f64(n, pos64, mass, eps, acc, pot, opts, stream, check=True):
     st = load().nbody_force_f64(n, pos64, mass, eps, acc, pot,
                                 ctypes.byref(opts) if opts is not None else None, stream)
     return _check(st, "nbody_force_f64") if check else st
+
+
+NBODY_NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def nbody_force_noalloc(n, pos, mass, eps, acc, pot, opts, stream, check=True):
+    st = load().nbody_force_noalloc(n, pos, mass, eps, acc, pot,
+                                    ctypes.byref(opts) if opts is not None else None, stream)
+    return _check(st, "nbody_force_noalloc") if check else st
 
 
 def nbody_force_ij(ni, pos_i, eps_i, nj, pos_j, mass_j, eps, acc, pot, opts, stream, check=True):

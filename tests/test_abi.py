@@ -429,3 +429,22 @@ def test_tuning_file_with_a_bad_entry_changes_nothing(tmp_path):
     _lib.nbody_tune_reset()
     if os.path.exists(_lib.TUNING_PATH):
         _lib.nbody_tune_load(_lib.TUNING_PATH)
+
+
+def test_noalloc_rejects_a_workspace_and_sizes_beyond_its_array():
+    o = _lib.nbody_opts_default()
+    o.workspace = FAKE * 256
+    o.workspace_bytes = 1 << 20
+    assert _lib.nbody_force_noalloc(1000, FAKE, FAKE, 0.1, FAKE, FAKE, o, None,
+                                    check=False) == _lib.NBODY_EINVAL
+    # 2^28 particles need 32 B of compensated partial sums each even with one j-segment:
+    # far beyond the static array; refused before anything touches the device.
+    assert _lib.nbody_force_noalloc(1 << 28, FAKE, FAKE, 0.1, FAKE, FAKE, None, None,
+                                    check=False) == _lib.NBODY_EINVAL
+    assert "static scratch" in _lib.nbody_last_error()
+    # an explicit j-split whose partial sums do not fit is refused, not shortened
+    o = _lib.nbody_opts_default()
+    o.jlanes, o.nseg = 1, 1024
+    assert _lib.nbody_force_noalloc(131072, FAKE, FAKE, 0.1, FAKE, FAKE, o, None,
+                                    check=False) == _lib.NBODY_EINVAL
+    assert _lib.nbody_force_noalloc(0, None, None, 0.1, None, None, None, None) == _lib.NBODY_OK
