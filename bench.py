@@ -204,6 +204,7 @@ class Timer:
 
 WARM_SECONDS = 0.25
 WARMED = []
+GRAPH_CALLS = 50  # evaluations per graph replay in the small-system timing
 
 
 def warm_up(torch, call, count):
@@ -384,7 +385,10 @@ def bench_plummer(args, torch, w):
 
 def bench_small(args, torch, w):
     """N = 2048 sphere: one force+potential evaluation per step (FP32 inputs), every mode,
-    against the oracle on all N^2 pairs."""
+    against the oracle on all N^2 pairs.  A step is timed inside a HIP graph of
+    GRAPH_CALLS back-to-back evaluations (the GPU's own rate: from Python each eager call
+    costs about 8 us of host time, more than the evaluation); the eager per-call time is
+    reported beside it."""
     from paper_astro_ph_0703100_amd import _lib, api, ics, metrics
     n = w.n
     pos, _, mass = ics.plummer(n, seed=w.seed, velocities=False)
@@ -400,15 +404,56 @@ def bench_small(args, torch, w):
     pairs = float(n) * n
     reps = max(args.steps, 200)
     res = {}
+    side = torch.cuda.Stream()
     for precision in modes_of(args):
+        shape = _lib.nbody_tune_get(_lib.NBODY_KERNEL_FORCE, _lib.PRECISIONS[precision], n)
         opts = api.make_opts(precision=precision)
+        ws = torch.empty(max(_lib.nbody_workspace_size(n, opts), 256), dtype=torch.uint8,
+                         device=dev)
+        gopts = api.make_opts(precision=precision, workspace=ws)
         call = lambda: _lib.nbody_force_ex(n, p.data_ptr(), m.data_ptr(), eps, acc.data_ptr(),
                                            pot.data_ptr(), opts, sp)
-        wall, kms = timer.run(call, reps, warmup=args.warmup)
-        res[precision] = {"wall": wall, "kernel_ms": float(np.mean(kms)),
-                          "acc": acc.cpu().numpy().T.copy(), "pot": pot.cpu().numpy().copy()}
-        print("bench: %-8s N=%d  %.2f us per evaluation (events)" % (precision, n, np.mean(kms) * 1e3),
+        _, kms = timer.run(call, reps, warmup=args.warmup)
+        eager_ms = float(np.mean(kms))
+        res_eager = (acc.cpu().numpy().T.copy(), pot.cpu().numpy().copy())
+        # the same evaluations replayed from a graph
+        graph = torch.cuda.CUDAGraph()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(side):
+            with torch.cuda.graph(graph, stream=side):
+                for _ in range(GRAPH_CALLS):
+                    _lib.nbody_force_ex(n, p.data_ptr(), m.data_ptr(), eps, acc.data_ptr(),
+                                        pot.data_ptr(), gopts, side.cuda_stream)
+        torch.cuda.synchronize()
+        _, gms = timer.run(graph.replay, max(4, reps // GRAPH_CALLS), warmup=args.warmup)
+        kernel_ms = float(np.mean(gms)) / GRAPH_CALLS
+        graph_res = (acc.cpu().numpy().T.copy(), pot.cpu().numpy().copy())
+        assert np.array_equal(graph_res[0], res_eager[0]) and \
+            np.array_equal(graph_res[1], res_eager[1]), "graph replay differs from eager calls"
+        res[precision] = {"kernel_ms": kernel_ms, "eager_ms": eager_ms, "shape": shape,
+                          "acc": graph_res[0], "pot": graph_res[1]}
+        del graph
+        print("bench: %-8s N=%d  %.2f us per evaluation in a graph, %.2f us eager (shape "
+              "ipl %d jtile %d nseg %d jlanes %d)" % ((precision, n, kernel_ms * 1e3,
+                                                       eager_ms * 1e3) + tuple(shape)),
               file=sys.stderr, flush=True)
+    # The launch floor: the same graph of evaluations of a one-particle system (one block,
+    # no pairs), i.e. what a launch costs the GPU whatever it computes.
+    one = torch.zeros((3, 1), dtype=torch.float32, device=dev)
+    one_m = torch.ones(1, dtype=torch.float32, device=dev)
+    graph = torch.cuda.CUDAGraph()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(graph, stream=side):
+            for _ in range(GRAPH_CALLS):
+                _lib.nbody_force_ex(1, one.data_ptr(), one_m.data_ptr(), eps, acc.data_ptr(),
+                                    pot.data_ptr(), api.make_opts(), side.cuda_stream)
+    torch.cuda.synchronize()
+    _, fms = timer.run(graph.replay, max(4, reps // GRAPH_CALLS), warmup=args.warmup)
+    floor_ms = float(np.mean(fms)) / GRAPH_CALLS
+    del graph
+    print("bench: launch floor (N = 1 evaluations in a graph) %.2f us" % (floor_ms * 1e3),
+          file=sys.stderr, flush=True)
     cpu, errors = None, {}
     if not args.no_cpu_baseline:
         import oracle
@@ -421,14 +466,20 @@ def bench_small(args, torch, w):
             errors[q] = errors_of(metrics, r["acc"], r["pot"], ra, rp)
     head = next(iter(res))
     r0 = res[head]
+    kname = ("split_kernel<Gravity, ForceOut> (one launch per evaluation)" if r0["shape"][3] > 1
+             else "tile_kernel<Gravity> + finalize_kernel")
     return {
-        "value": pairs * reps / r0["wall"], "ms_per_step": r0["kernel_ms"],
+        "value": pairs / (r0["kernel_ms"] * 1e-3), "ms_per_step": r0["kernel_ms"],
         "config": {"workload": w.name, "n": n, "eps": eps, "seed": w.seed, "precision": head,
-                   "step": "one force+potential evaluation (nbody_force_ex, FP32 inputs)",
+                   "step": "one force+potential evaluation (nbody_force_ex, FP32 inputs), "
+                           "%d per HIP graph replay" % GRAPH_CALLS,
                    "description": w.description},
-        "roofline": roofline("gravity", pairs, r0["kernel_ms"], "force evaluation (all kernels)"),
+        "roofline": roofline("gravity", pairs, r0["kernel_ms"], kname),
+        "launch_floor_ms": floor_ms,
         "cpu_baseline": cpu,
-        "modes": {q: {"ms_per_step": r["kernel_ms"], **fractions("gravity", pairs, r["kernel_ms"]),
+        "modes": {q: {"ms_per_step": r["kernel_ms"], "eager_ms_per_call": r["eager_ms"],
+                      "shape": dict(zip(("ipl", "jtile", "nseg", "jlanes"), r["shape"])),
+                      **fractions("gravity", pairs, r["kernel_ms"]),
                       "errors": errors.get(q)} for q, r in res.items()},
     }
 
@@ -969,7 +1020,7 @@ def compact(body):
            "modes": {k: {kk: vv for kk, vv in v.items() if kk != "value"}
                      for k, v in body["modes"].items()},
            "oracle_sample": (body.get("cpu_baseline") or {}).get("sample")}
-    for key in ("error_split", "adjoint_kernel_131072"):
+    for key in ("error_split", "adjoint_kernel_131072", "launch_floor_ms"):
         if body.get(key) is not None:
             out[key] = body[key]
     return out

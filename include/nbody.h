@@ -93,8 +93,9 @@ typedef struct nbody_opts {
  *     and walks one of nseg j-segments in LDS tiles of jtile records (64 to 512);
  *     the segment partial sums go to scratch memory and a second kernel adds them
  *     per particle in FP64 (the paper's i-parallel FORCE-LOOP, Sec. 2.2);
- *   - the split engine (jlanes = 8, 16, 32 or 64; ipl = 1 or 2; jtile = 256, 512 or
- *     1024, at most 512 for the adjoint; nseg must be 0): for systems too small to
+ *   - the split engine (jlanes = 8, 16, 32 or 64; ipl = 1 or 2; jtile = 256, 512,
+ *     1024, or 2048 with jlanes >= 32; the adjoint: 256 or 512; nseg must be 0): for
+ *     systems too small to
  *     fill the chip with whole i-tiles, the j-range of each i-particle is split over
  *     jlanes lanes of one wavefront, whose partial sums are added across the lanes
  *     in FP64 (PLAIN: FP32) by DPP / permlane moves in a fixed order.  One launch, no

@@ -300,14 +300,18 @@ __global__ __launch_bounds__(kTPB) void split_kernel(typename Op::Args a, typena
     }
 }
 
-// Launch-shape dispatch: IPL in {1, 2}, Q in {8, 16, 32, 64}, JT in {256, 512, 1024}
-// (JT * kJWords * 8 bytes of LDS, at most 32 KB: four or more blocks per CU).
+// Launch-shape dispatch: IPL in {1, 2}, Q in {8, 16, 32, 64}, JT in {256, 512, 1024,
+// 2048} (JT * kJWords * 8 bytes of LDS: at most 32 KB, four or more blocks per CU; or
+// 64 KB for 2048 16-byte records and Q >= 32, the tiny systems where one or two tiles
+// hold every j and a block's loads should all be in flight at once).
 template <class Op, class Sink>
 using SplitFn = void (*)(typename Op::Args, typename Sink::Args);
 
 template <class Op, class Sink, int IPL, int Q, int JT>
 SplitFn<Op, Sink> spick_mode(int mode, bool full) {
-    if constexpr (JT * Op::kJWords * 8 > 32768) {
+    constexpr bool kFits = JT * Op::kJWords * 8 <= 32768 ||
+                           (JT == 2048 && Op::kJWords == 4 && Q >= 32);
+    if constexpr (!kFits) {
         return nullptr;
     } else {
         switch (mode) {
@@ -331,6 +335,7 @@ SplitFn<Op, Sink> spick_jt(int jt, int mode, bool full) {
         case 256: return spick_mode<Op, Sink, IPL, Q, 256>(mode, full);
         case 512: return spick_mode<Op, Sink, IPL, Q, 512>(mode, full);
         case 1024: return spick_mode<Op, Sink, IPL, Q, 1024>(mode, full);
+        case 2048: return spick_mode<Op, Sink, IPL, Q, 2048>(mode, full);
     }
     return nullptr;
 }

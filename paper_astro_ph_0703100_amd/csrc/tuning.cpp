@@ -31,10 +31,14 @@ TuneEntry builtin(int kernel, int64_t n, bool split_ok) {
     // Measured on MI355X (tune.py): one i-particle per lane (37 VGPRs, 8 waves per
     // SIMD) and many j-segments beat wider i-tiles for every kernel and size tried;
     // the j-split itself is chosen from n (nseg = 0).  Below 2^13 particles the force's
-    // single-launch split engine is faster (N = 2048: 7.0 against 10.2 us per
-    // evaluation; N = 4096: 10.8 against 12.7 us); from 2^13 on the grid engine is.
-    if (kernel == KERNEL_FORCE && split_ok && n < (int64_t(1) << 13))
-        return n < (int64_t(1) << 12) ? TuneEntry{1, 512, 0, 64} : TuneEntry{1, 1024, 0, 32};
+    // single-launch split engine is faster (graph-replayed evaluations, N = 2048: 5.4
+    // against 9.5 us; N = 4096: 10.7 against 13.0 us); from 2^13 on the grid engine is.
+    // The 2048-record tile (64 KB of LDS, two blocks per CU) only while every block fits
+    // in one round.
+    if (kernel == KERNEL_FORCE && split_ok && n < (int64_t(1) << 13)) {
+        if (n <= 2048) return TuneEntry{1, 2048, 0, 64};
+        return n < 4096 ? TuneEntry{1, 1024, 0, 64} : TuneEntry{1, 1024, 0, 32};
+    }
     if (kernel == KERNEL_BATCHED) return {1, 64, 0};
     return {1, 256, 0};
 }
@@ -52,10 +56,13 @@ bool valid_shape(int kernel, const TuneEntry &e) {
                (e.jt == 64 || e.jt == 128 || e.jt == 256 || e.jt == 512) && e.nseg >= 0 &&
                e.nseg <= kMaxSeg;
     // Split engine: force and adjoint only; the adjoint's 32-byte j-records cap the
-    // double-buffered tile at 512 records (32 KB of LDS).
+    // double-buffered tile at 512 records (32 KB of LDS); the force's 2048-record tile
+    // (64 KB) is built for 32 and 64 lanes per i-particle.
     if (kernel != KERNEL_FORCE && kernel != KERNEL_VJP) return false;
+    const bool jt_ok = e.jt == 256 || e.jt == 512 ||
+                       (kernel == KERNEL_FORCE && (e.jt == 1024 || (e.jt == 2048 && e.jl >= 32)));
     return (e.jl == 8 || e.jl == 16 || e.jl == 32 || e.jl == 64) && (e.ipl == 1 || e.ipl == 2) &&
-           (e.jt == 256 || e.jt == 512 || (e.jt == 1024 && kernel == KERNEL_FORCE)) && e.nseg == 0;
+           jt_ok && e.nseg == 0;
 }
 
 int size_bucket(int64_t n) {

@@ -4,9 +4,10 @@ For each workload it sweeps i-particles per lane (1, 2, 4, 8), j-tile (64 .. 512
 and, for the single-system kernels (force, force-jerk, adjoint), the number of
 j-segments of the grid engine; for the force and the adjoint up to 2^15 particles
 also the split engine's shapes (lanes per i-particle 8 .. 64, i-particles per lane 1
-or 2, j-tile 256 .. 1024).  Every shape is timed with HIP events on the launch stream
-(median of ``reps`` runs of back-to-back calls, each run at least about a millisecond
-long, after a warm-up call); and admits
+or 2, j-tile 256 .. 2048).  Every shape is timed with HIP events on the launch stream
+(median of ``reps`` runs, after a warm-up call): the force and the adjoint as HIP graphs
+of back-to-back calls (the GPU's own time; a small evaluation takes less than the
+host's launch cost), the others as runs of back-to-back calls; and admits
 a shape only if its result matches a reference computed on the same GPU with FP64
 reduction at the built-in shape (relative RMS <= 1e-6, plain FP32 <= 2e-5).  The
 fastest admitted shape is stored with ``nbody_tune_set`` and the table is written
@@ -32,7 +33,8 @@ JTILES = (64, 128, 256, 512)
 SEGS = (0, 4, 8, 10, 12, 16, 20, 24, 32, 40, 48, 64, 96, 128)
 # Split engine: (ipl, jlanes, jtile); the adjoint's 32-byte j-records stop at 512.
 SPLIT_MAX_N = 1 << 15
-SPLIT = [(ipl, jl, jt) for ipl in (1, 2) for jl in (8, 16, 32, 64) for jt in (256, 512, 1024)]
+SPLIT = [(ipl, jl, jt) for ipl in (1, 2) for jl in (8, 16, 32, 64) for jt in (256, 512, 1024, 2048)
+         if jt < 2048 or jl >= 32]
 GATE = {"comp": 1e-6, "fp64red": 1e-6, "plain": 2e-5}
 
 
@@ -49,6 +51,8 @@ def shapes(n: int, kernel: str):
         for ipl, jl, jt in SPLIT:
             if kernel == "vjp" and jt > 512:
                 continue
+            if jt == 2048 and n > 8192:
+                continue  # one block per CU pair of tiles: only for the smallest systems
             out.append({"ipl": ipl, "jtile": jt, "nseg": 0, "jlanes": jl})
     return out
 
@@ -77,6 +81,46 @@ def _time(call, reps: int) -> float:
     return float(np.median(times))
 
 
+def _time_graph(make_call, reps: int) -> float:
+    """Median milliseconds per call of ``make_call(stream)()`` replayed from a HIP graph of
+    back-to-back calls (about half a millisecond or more per replay): the GPU's own time
+    per call, without the host's launch cost, which exceeds a small evaluation's."""
+    side = torch.cuda.Stream()
+    s = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(side):
+        call = make_call(side.cuda_stream)
+        call()
+        side.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(side)
+        call()
+        b.record(side)
+        b.synchronize()
+        k = max(1, min(50, int(np.ceil(0.5 / max(a.elapsed_time(b), 1e-3)))))
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=side):
+            for _ in range(k):
+                call()
+    torch.cuda.synchronize()
+    g.replay()
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(s)
+        g.replay()
+        b.record(s)
+        b.synchronize()
+        times.append(a.elapsed_time(b) / k)
+    del g
+    return float(np.median(times))
+
+
+def _workspace(nbytes):
+    return torch.empty(max(256, nbytes), dtype=torch.uint8, device="cuda:0")
+
+
 def _host(t):
     return t.detach().cpu().numpy()
 
@@ -94,10 +138,10 @@ def tune_force(n: int, seed: int, eps: float, precision: str, reps: int = 3, log
     best = None
     rows = []
     for sh in shapes(n, "force"):
-        opts = api.make_opts(precision=precision, **sh)
-        call = lambda: _lib.nbody_force_ex(n, p.data_ptr(), m.data_ptr(), eps, acc.data_ptr(),
-                                           pot.data_ptr(), opts, api.stream_ptr())
-        ms = _time(call, reps)
+        ws = _workspace(_lib.nbody_workspace_size(n, api.make_opts(precision=precision, **sh)))
+        opts = api.make_opts(precision=precision, workspace=ws, **sh)
+        ms = _time_graph(lambda st: lambda: _lib.nbody_force_ex(
+            n, p.data_ptr(), m.data_ptr(), eps, acc.data_ptr(), pot.data_ptr(), opts, st), reps)
         ea = rel_errors(_host(acc).T, ref_a)["rel_rms"]
         ep = rel_errors(_host(pot), ref_p)["rel_rms"]
         ok = ea <= GATE[precision] and ep <= GATE[precision]
@@ -159,16 +203,18 @@ def tune_vjp(n: int, seed: int, eps: float, precision: str, reps: int = 3, log=N
     gx = torch.empty((3, n), dtype=torch.float64, device=dev)
     gm = torch.empty(n, dtype=torch.float64, device=dev)
 
-    def run(opts):
+    def run(opts, stream=None):
         return lambda: _lib.nbody_force_vjp(n, p.data_ptr(), m.data_ptr(), eps, g.data_ptr(),
                                             None, gx.data_ptr(), gm.data_ptr(), opts,
-                                            api.stream_ptr())
+                                            stream if stream is not None else api.stream_ptr())
     run(api.make_opts(precision="fp64red", ipl=1, jtile=64, nseg=1))()
     torch.cuda.synchronize()
     ref = _host(gx).T.copy()
     best, rows = None, []
     for sh in shapes(n, "vjp"):
-        ms = _time(run(api.make_opts(precision=precision, **sh)), reps)
+        ws = _workspace(_lib.nbody_workspace_size_vjp(n, api.make_opts(precision=precision, **sh)))
+        opts = api.make_opts(precision=precision, workspace=ws, **sh)
+        ms = _time_graph(lambda st: run(opts, st), reps)
         e = rel_errors(_host(gx).T, ref)["normwise"]
         ok = e <= 1e-6
         row = dict({"kernel": "vjp", "precision": precision, "n": n}, **sh)
@@ -246,7 +292,9 @@ def main(argv=None):
     for prec in ("comp", "plain", "fp64red"):
         jobs.append(("force", prec, lambda prec=prec: tune_force(w.n, w.seed, eps, prec, args.reps, log)))
     if not args.quick:
-        for n in (2048, 4096, 8192, 16384, 32768):
+        # Below 2^13 particles the built-in split-engine shapes are used (they depend on n
+        # within a size bucket: the 2048-record tile only while the blocks fit one round).
+        for n in (8192, 16384, 32768):
             jobs.append(("force", "comp", lambda n=n: tune_force(n, 10 + n, 0.01, "comp", args.reps, log)))
         jobs.append(("jerk", "comp", lambda: tune_jerk(w.n, w.seed, eps, "comp", args.reps, log)))
         wa = ics.WORKLOADS["adjoint_16384"]

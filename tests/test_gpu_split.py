@@ -23,8 +23,9 @@ DEV = "cuda:0"
 TOL = {"comp": 1e-6, "fp64red": 1e-6, "plain": 1e-5}
 U = bounds.U
 
-SHAPES = [(1, 8, 256), (1, 8, 1024), (1, 16, 512), (1, 32, 256), (1, 32, 1024),
-          (1, 64, 256), (1, 64, 512), (2, 8, 512), (2, 16, 256), (2, 32, 512), (2, 64, 1024)]
+SHAPES = [(1, 8, 256), (1, 8, 1024), (1, 16, 512), (1, 32, 256), (1, 32, 1024), (1, 32, 2048),
+          (1, 64, 256), (1, 64, 512), (1, 64, 2048), (2, 8, 512), (2, 16, 256), (2, 32, 512),
+          (2, 64, 1024), (2, 64, 2048)]
 
 
 def split_adds(precision, n, jlanes, jtile):
