@@ -84,6 +84,29 @@ def test_stress_1m_centre_modes(stress, precision):
     assert errs["none"][1]["rel_rms"] > 1e-2  # FP32 coordinates near 1000 cannot resolve the core
 
 
+@pytest.mark.parametrize("precision", ["comp", "fp64red"])
+def test_stress_1m_arithmetic_error_apart_from_representation(stress, precision):
+    """The same evaluations against the oracle run on the FP32 inputs the kernel sees
+    (fp32(x - c), c the FP64 mean of all positions, for the system centre; fp32(x)
+    without one): what is left is the kernel's own arithmetic, which stays at the
+    force tolerance even where the representation error of the inputs (about 1e-6 with
+    the system centre, 1e-2 without) does not."""
+    s = stress
+    x = s["x"].cpu().numpy().T
+    m64 = s["m"].cpu().numpy().astype(np.float64)
+    for centre, c in (("system", x.mean(axis=0)), ("none", np.zeros(3))):
+        x32 = (x - c).astype(np.float32).astype(np.float64)
+        ra, rp = oracle.force_sampled(x32, m64, s["eps"], s["idx"])
+        acc, pot = api.force_f64(s["x"], s["m"], s["eps"], precision=precision, centre=centre)
+        torch.cuda.synchronize()
+        ea = rel_errors(acc.cpu().numpy().T[s["idx"]], ra)
+        ep = rel_errors(pot.cpu().numpy()[s["idx"]] , rp)
+        e_rep = rel_errors(ra, s["ra"])
+        print(precision, centre, "arithmetic %.3e (pot %.3e), representation %.3e"
+              % (ea["rel_rms"], ep["rel_rms"], e_rep["rel_rms"]))
+        assert ea["rel_rms"] <= 1e-6 and ep["rel_rms"] <= 1e-6
+
+
 def test_leapfrog_with_tile_centres_matches_oracle():
     n, steps, dt = 3000, 8, 1.0 / 256
     pos, vel, mass = ics.plummer(n, seed=91)
