@@ -35,8 +35,14 @@ TuneEntry builtin(int kernel, int64_t n, bool split_ok) {
     // against 9.5 us; N = 4096: 10.7 against 13.0 us); from 2^13 on the grid engine is.
     // The 2048-record tile (64 KB of LDS, two blocks per CU) only while every block fits
     // in one round.
+    // Up to 2048 particles the tile is the smallest that holds every j (padding records
+    // cost pair work too).
     if (kernel == KERNEL_FORCE && split_ok && n < (int64_t(1) << 13)) {
-        if (n <= 2048) return TuneEntry{1, 2048, 0, 64};
+        if (n <= 2048) {
+            int jt = 256;
+            while (jt < n) jt *= 2;
+            return TuneEntry{1, jt, 0, 64};
+        }
         return n < 4096 ? TuneEntry{1, 1024, 0, 64} : TuneEntry{1, 1024, 0, 32};
     }
     if (kernel == KERNEL_BATCHED) return {1, 64, 0};
