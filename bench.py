@@ -204,7 +204,9 @@ class Timer:
 
 WARM_SECONDS = 0.25
 WARMED = []
-GRAPH_CALLS = 50  # evaluations per graph replay in the small-system timing
+GRAPH_CALLS = 50    # evaluations per graph replay in the small-system timing
+GRAPH_REPLAYS = 40  # timed replays; the median is reported (a replay's 50 launches are
+                    # submitted by the host, whose pace varies from run to run)
 
 
 def warm_up(torch, call, count):
@@ -425,8 +427,8 @@ def bench_small(args, torch, w):
                     _lib.nbody_force_ex(n, p.data_ptr(), m.data_ptr(), eps, acc.data_ptr(),
                                         pot.data_ptr(), gopts, side.cuda_stream)
         torch.cuda.synchronize()
-        _, gms = timer.run(graph.replay, max(4, reps // GRAPH_CALLS), warmup=args.warmup)
-        kernel_ms = float(np.mean(gms)) / GRAPH_CALLS
+        _, gms = timer.run(graph.replay, GRAPH_REPLAYS, warmup=args.warmup)
+        kernel_ms = float(np.median(gms)) / GRAPH_CALLS
         graph_res = (acc.cpu().numpy().T.copy(), pot.cpu().numpy().copy())
         assert np.array_equal(graph_res[0], res_eager[0]) and \
             np.array_equal(graph_res[1], res_eager[1]), "graph replay differs from eager calls"
@@ -449,8 +451,8 @@ def bench_small(args, torch, w):
                 _lib.nbody_force_ex(1, one.data_ptr(), one_m.data_ptr(), eps, acc.data_ptr(),
                                     pot.data_ptr(), api.make_opts(), side.cuda_stream)
     torch.cuda.synchronize()
-    _, fms = timer.run(graph.replay, max(4, reps // GRAPH_CALLS), warmup=args.warmup)
-    floor_ms = float(np.mean(fms)) / GRAPH_CALLS
+    _, fms = timer.run(graph.replay, GRAPH_REPLAYS, warmup=args.warmup)
+    floor_ms = float(np.median(fms)) / GRAPH_CALLS
     del graph
     print("bench: launch floor (N = 1 evaluations in a graph) %.2f us" % (floor_ms * 1e3),
           file=sys.stderr, flush=True)

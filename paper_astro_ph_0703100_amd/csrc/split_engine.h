@@ -103,10 +103,6 @@ __device__ __forceinline__ T group_sum(T v) {
     return v;
 }
 
-// s_waitcnt vmcnt(0) (expcnt and lgkmcnt left at their maxima, 7 and 15, in the gfx9
-// encoding): wait for every outstanding vector-memory load of the wave.
-constexpr int kWaitVmem = 0x0F70;
-
 // Records a lane reads from LDS before it runs their pairs: with few waves per SIMD
 // (the small systems this engine is for) the LDS latency is not hidden by other waves,
 // so each group of kAhead independent pairs is issued after one wait.
@@ -257,7 +253,7 @@ __global__ __launch_bounds__(kTPB) void split_kernel(typename Op::Args a, typena
     // Every load issued so far (the i-records, the first tile) has completed here; saying
     // so keeps the compiler from waiting on the i-record loads inside the tile loop,
     // where the in-order load counter would also hold back the next tile's loads.
-    __builtin_amdgcn_s_waitcnt(kWaitVmem);
+    __builtin_amdgcn_s_waitcnt(engine::kWaitVmem);
     for (int t = 0; t < ntiles; ++t) {
         const int buf = t & 1;
         if (t + 1 < ntiles) fetch(t + 1);

@@ -54,6 +54,14 @@
 namespace nbody {
 namespace engine {
 
+// s_waitcnt vmcnt(0) (expcnt and lgkmcnt left at their maxima, 7 and 15, in the gfx9
+// encoding): wait for every outstanding vector-memory load of the wave.  Issued once
+// after the first j-tile is staged, it tells the compiler that the i-record loads have
+// completed; otherwise it waits on them inside the tile loop, where the in-order load
+// counter also holds back the prefetch of the next tile (its latency then shows at
+// every tile).
+constexpr int kWaitVmem = 0x0F70;
+
 // Knuth's error-free sum: hi + lo += b with hi = fl(hi + b) and the rounding error of
 // that addition added to lo.
 __device__ __forceinline__ void two_sum(float &hi, float &lo, float b) {
@@ -224,6 +232,7 @@ __device__ __forceinline__ void block_work(const typename Op::Args &a, float4 (*
         store(0);
     }
     __syncthreads();
+    __builtin_amdgcn_s_waitcnt(kWaitVmem);
     for (int t = 0; t < ntiles; ++t) {
         const int buf = t & 1;
         if (t + 1 < ntiles) fetch(t + 1);
