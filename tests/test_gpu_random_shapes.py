@@ -166,3 +166,59 @@ def test_force_jerk_ij(k):
     err = np.sqrt(((jerk.cpu().numpy().T - rj) ** 2).sum(1))
     cmax = 74.0 + (c["n"] + 1024 if c["precision"] == "plain" else min(128, c["jtile"]) - 1)
     assert np.all(err <= cmax * U * scale), (c, float((err / (U * scale + 1e-300)).max()))
+
+
+def draw_split(rng):
+    jl = int(rng.choice([8, 16, 32, 64]))
+    jts = [256, 512, 1024] + ([2048] if jl >= 32 else [])
+    return {"n": int(rng.integers(2, 9000)), "ipl": int(rng.choice([1, 2])), "jlanes": jl,
+            "jtile": int(rng.choice(jts)),
+            "precision": str(rng.choice(["comp", "fp64red", "plain"])),
+            "eps": float(np.float32(10 ** rng.uniform(-3, -1)))}
+
+
+SPLIT_CASES = [draw_split(np.random.default_rng(11000 + k)) for k in range(16)]
+
+
+@pytest.mark.parametrize("k", range(len(SPLIT_CASES)))
+def test_split_force(k):
+    # The split engine: a lane's FP32 block is its share of a tile, jtile / jlanes terms
+    # (at most 128), then two-sum or FP64; plain FP32 sums the lane's whole share and the
+    # jlanes shares in FP32.
+    c = SPLIT_CASES[k]
+    x, _, m = sphere(c["n"], 12000 + k)
+    shape = dict(ipl=c["ipl"], jtile=c["jtile"], jlanes=c["jlanes"])
+    acc, pot = api.force(t32(x), torch.from_numpy(m.astype(np.float32)).to(DEV), c["eps"],
+                         precision=c["precision"], **shape)
+    torch.cuda.synchronize()
+    ra, rp = oracle.force_all(x, m, c["eps"])
+    ea = rel_errors(acc.cpu().numpy().T, ra)
+    adds = min(128, c["jtile"] // c["jlanes"]) - 1 if c["precision"] != "plain" else c["n"] + 64
+    bound = (bounds.C_POT + adds) * U * np.abs(rp)
+    assert ea["rel_rms"] <= TOL[c["precision"]], (c, ea)
+    perr = np.abs(pot.cpu().numpy() - rp)
+    assert np.all(perr <= bound), (c, float((perr / bound).max()))
+
+
+@pytest.mark.parametrize("k", range(0, len(SPLIT_CASES), 2))
+def test_split_vjp(k):
+    c = dict(SPLIT_CASES[k])
+    c["jtile"] = min(c["jtile"], 512)  # the adjoint's 32-byte records: tiles up to 512
+    n = c["n"]
+    x, _, m = sphere(n, 13000 + k)
+    rng = np.random.default_rng(14000 + k)
+    ga = rng.standard_normal((n, 3)).astype(np.float32).astype(np.float64)
+    gp = rng.standard_normal(n).astype(np.float32).astype(np.float64)
+    gx = torch.empty((3, n), dtype=torch.float64, device=DEV)
+    gm = torch.empty(n, dtype=torch.float64, device=DEV)
+    opts = api.make_opts(precision=c["precision"], ipl=c["ipl"], jtile=c["jtile"],
+                         jlanes=c["jlanes"])
+    p, mm = t32(x), torch.from_numpy(m.astype(np.float32)).to(DEV)
+    g, gpt = torch.from_numpy(np.ascontiguousarray(ga.T)).to(DEV), torch.from_numpy(gp).to(DEV)
+    _lib.nbody_force_vjp(n, p.data_ptr(), mm.data_ptr(), c["eps"], g.data_ptr(), gpt.data_ptr(),
+                         gx.data_ptr(), gm.data_ptr(), opts, api.stream_ptr())
+    torch.cuda.synchronize()
+    rx, rm = oracle.vjp(x, m, c["eps"], ga, gp)
+    tol = 1e-4 if c["precision"] == "plain" else 1e-5
+    assert rel_errors(gx.cpu().numpy().T, rx)["rel_rms"] <= tol, c
+    assert scaled_max(gm.cpu().numpy(), rm) <= tol, c
