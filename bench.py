@@ -35,7 +35,7 @@ paper's count; 60 per force-jerk-potential pair; 45 per adjoint pair) is compare
 with the published FP32 vector peak of the MI355X, 157.3 TFLOP/s (``frac``).  Beside
 it, ``issue_model`` compares the pair rate with the VALU issue limit of the pair body:
 13 FP32 VALU instructions at 32 lanes per clock and one quarter-rate v_rsq_f32 (17
-issue slots per gravity pair; 31 per force-jerk-potential pair, 42 per adjoint pair)
+issue slots per gravity pair; 31 per force-jerk-potential pair, 35 per adjoint pair)
 at 256 CUs x 4 SIMDs x 2.4 GHz.  ``traffic`` comes from the committed rocprofv3
 counter summary of the same kernel and is null when its sources changed since.
 
@@ -78,7 +78,7 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3
 CUS, SIMDS, LANES, CLOCK_HZ = 256, 4, 32, 2.4e9
 LANE_ISSUE = CUS * SIMDS * LANES * CLOCK_HZ
 RSQ_SLOTS = 4
-SLOTS = {"gravity": 13 + RSQ_SLOTS, "jerk": 27 + RSQ_SLOTS, "adjoint": 38 + RSQ_SLOTS}
+SLOTS = {"gravity": 13 + RSQ_SLOTS, "jerk": 27 + RSQ_SLOTS, "adjoint": 31 + RSQ_SLOTS}
 # Flops per pair: the paper's count for gravity (Sec. 1.1); 60 for force, jerk and
 # potential, the count customary for fourth-order Hermite codes; 45 for the adjoint.
 FLOPS = {"gravity": 20, "jerk": 60, "adjoint": 45}

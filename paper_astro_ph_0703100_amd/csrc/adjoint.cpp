@@ -21,7 +21,7 @@ nbody_status check_vjp(int64_t n, const void *pos, const float *mass, float eps,
 }
 
 size_t vjp_f64_bytes(int64_t n, const TileCfg &cfg, int precision) {
-    return f64_scratch_bytes(n, cfg, precision);
+    return f64_scratch_bytes(n, cfg, precision, kVjpOutputs);
 }
 
 // Adjoint pair kernel + FP64 finalize on FP32 positions.
@@ -32,8 +32,8 @@ nbody_status vjp_f32_core(int64_t n, const float *pos, const float *mass, float 
     const float e2 = eps * eps;
     VjpArgs va{pos,   pos + n, pos + 2 * n, mass, g_acc, g_acc + n, g_acc + 2 * n,
                g_pot, (int)n,  cfg.seg_len, e2,   part,  cfg.npad};
-    VjpFinalizeArgs fa{part, cfg.nseg, cfg.npad, (int)n, g_pot, grad_pos, grad_mass,
-                       accumulate ? 1 : 0};
+    VjpFinalizeArgs fa{part,      cfg.nseg, cfg.npad,           (int)n, g_pot,
+                       grad_pos,  grad_mass, accumulate ? 1 : 0, g_acc};
     if (cfg.jl > 1) return launch_vjp_split(cfg, o.precision, va, grad_mass != nullptr, fa, s);
     nbody_status st = launch_vjp(cfg, o.precision, va, grad_mass != nullptr, s);
     if (st) return st;
@@ -58,8 +58,8 @@ nbody_status vjp_f64_core(int64_t n, const double *pos64, const float *mass, flo
         VjpTileArgs va{pos64, pos64 + n, pos64 + 2 * n, mass, g_acc, g_acc + n, g_acc + 2 * n,
                        g_pot, (int)n, cfg.seg_len, e2, ws.part, cfg.npad, centres, itile};
         if ((st = launch_vjp_tile(cfg, o.precision, va, grad_mass != nullptr, s))) return st;
-        VjpFinalizeArgs fa{ws.part, cfg.nseg, cfg.npad, (int)n, g_pot, grad_pos, grad_mass,
-                           accumulate ? 1 : 0};
+        VjpFinalizeArgs fa{ws.part,  cfg.nseg, cfg.npad,           (int)n, g_pot,
+                           grad_pos, grad_mass, accumulate ? 1 : 0, g_acc};
         return launch_vjp_finalize(o.precision, fa, s);
     }
     if (o.centre == NBODY_CENTRE_SYSTEM) {
@@ -106,7 +106,7 @@ nbody_status nbody_force_vjp(int64_t n, const float *pos, const float *mass, flo
     TileCfg cfg;
     if ((st = choose_cfg(KERNEL_VJP, n, o.precision, o, &cfg, true))) return st;
     void *ws = nullptr;
-    if ((st = get_workspace(o, partial_bytes(cfg, o.precision), s, &ws))) return st;
+    if ((st = get_workspace(o, partial_bytes(cfg, o.precision, kVjpOutputs), s, &ws))) return st;
     return vjp_f32_core(n, pos, mass, eps, g_acc, g_pot, grad_pos, grad_mass, false, o, cfg, ws, s);
 }
 
@@ -125,7 +125,7 @@ nbody_status nbody_force_vjp_f64(int64_t n, const double *pos64, const float *ma
     void *ws = nullptr;
     if ((st = get_workspace(o, vjp_f64_bytes(n, cfg, o.precision), s, &ws))) return st;
     return vjp_f64_core(n, pos64, mass, eps, g_acc, g_pot, grad_pos, grad_mass, false, o, cfg,
-                        f64_scratch_layout(ws, n, cfg, o.precision), s);
+                        f64_scratch_layout(ws, n, cfg, o.precision, kVjpOutputs), s);
 }
 
 nbody_status nbody_leapfrog_adjoint(int64_t n, const double *traj, const float *mass, float eps,
@@ -151,7 +151,7 @@ nbody_status nbody_leapfrog_adjoint(int64_t n, const double *traj, const float *
     const size_t n3 = 3 * (size_t)n;
     void *ws = nullptr;
     if ((st = get_workspace(o, base + sizeof(double) * n3, s, &ws))) return st;
-    const F64Scratch lay = f64_scratch_layout(ws, n, cfg, o.precision);
+    const F64Scratch lay = f64_scratch_layout(ws, n, cfg, o.precision, kVjpOutputs);
     double *abar = reinterpret_cast<double *>(static_cast<char *>(ws) + base);
     const double h = 0.5 * dt;
 

@@ -8,9 +8,14 @@
 //              w_kj = m_k g_j - m_j g_k
 //           =  sum_{j != k} [ w / s^3 - (q / s^3 + 3 (d . w) / s^5) d ],  q = m_k p_j + m_j p_k
 //   dL/dm_k = -sum_{j != k} [ (g_j . d) / s^3 + p_j / s ].
-// The engine hands the j == k pair a record with no mass and no cotangents (null_j):
-// with d = 0 exactly, w = m_k * 0 - 0 * g_k = 0, q = 0 and p_j = 0 it adds exactly
-// zero to both sums.  38 VALU operations and one v_rsq_f32 per pair.
+// The term w / s^3 splits into m_k g_j / s^3, accumulated per pair (3 FMAs), and
+// -g_k m_j / s^3, whose scalar sum B_k = sum_j m_j / s^3 is accumulated (1 FMA) and
+// multiplied by the particle's own g_k once, in FP64, by the output stage; d . w =
+// m_k (d . g_j) - m_j (d . g_k), where d . g_j is the dL/dm term's too.  Outputs:
+// [0..2] sum_j (m_k g_j / s^3 - e d) with e = (q + 3 (d . w) / s^2) / s^3, [3] B_k,
+// [4] the positive sum of dL/dm_k.  The engine hands the j == k pair a record with no
+// mass and no cotangents (null_j), which adds exactly zero to every sum.
+// 31 VALU operations and one v_rsq_f32 per pair (38 when w was formed per pair).
 #pragma once
 
 #include "tile_engine.h"
@@ -21,7 +26,7 @@ namespace {
 
 struct Adjoint {
     static constexpr int kJWords = 8;  // x, y, z, m, gx, gy, gz, p
-    static constexpr int kOut = 4;     // dL/dx (3) and the positive sum of dL/dm
+    static constexpr int kOut = 5;     // see above: three position sums, B_k, mass sum
     // 128 j's per compensation step (32 before: 1.8 % slower at N = 16384 and 131072).
     static constexpr int kBlockJ = nbody::kBlockJ;
     using Args = VjpArgs;
@@ -60,7 +65,7 @@ struct Adjoint {
 
     template <bool MASS>
     static __device__ __forceinline__ void pair(const float *j, const IState &k, float eps2,
-                                                float (&acc)[4]) {
+                                                float (&acc)[5]) {
         const float dx = j[0] - k.x;
         const float dy = j[1] - k.y;
         const float dz = j[2] - k.z;
@@ -70,38 +75,29 @@ struct Adjoint {
         const float r = __builtin_amdgcn_rsqf(s2);
         const float r2 = r * r;
         const float r3 = r * r2;
-        const float t3 = r2 * 3.0f;
-        const float r5x3 = r3 * t3;  // 3 / s^5
-        // w = m_k g_j - m_j g_k from separately rounded products.
-        const float p1x = k.m * j[4];
-        const float p1y = k.m * j[5];
-        const float p1z = k.m * j[6];
-        const float p2x = j[3] * k.gx;
-        const float p2y = j[3] * k.gy;
-        const float p2z = j[3] * k.gz;
-        const float wx = p1x - p2x;
-        const float wy = p1y - p2y;
-        const float wz = p1z - p2z;
-        float dw = dx * wx;
-        dw = __builtin_fmaf(dy, wy, dw);
-        dw = __builtin_fmaf(dz, wz, dw);
+        const float kr3 = k.m * r3;  // m_k / s^3
+        float gd = j[4] * dx;        // d . g_j
+        gd = __builtin_fmaf(j[5], dy, gd);
+        gd = __builtin_fmaf(j[6], dz, gd);
+        float gkd = k.gx * dx;       // d . g_k
+        gkd = __builtin_fmaf(k.gy, dy, gkd);
+        gkd = __builtin_fmaf(k.gz, dz, gkd);
+        const float mgkd = j[3] * gkd;
+        const float dw = __builtin_fmaf(k.m, gd, -mgkd);  // d . w
         const float mp = j[3] * k.p;
         const float q = __builtin_fmaf(k.m, j[7], mp);
-        const float c3 = r5x3 * dw;
-        const float e = __builtin_fmaf(r3, q, c3);
-        acc[0] = __builtin_fmaf(r3, wx, acc[0]);
-        acc[1] = __builtin_fmaf(r3, wy, acc[1]);
-        acc[2] = __builtin_fmaf(r3, wz, acc[2]);
+        const float t3 = r2 * 3.0f;
+        const float e = r3 * __builtin_fmaf(t3, dw, q);
+        acc[0] = __builtin_fmaf(kr3, j[4], acc[0]);
+        acc[1] = __builtin_fmaf(kr3, j[5], acc[1]);
+        acc[2] = __builtin_fmaf(kr3, j[6], acc[2]);
         acc[0] = __builtin_fmaf(-e, dx, acc[0]);
         acc[1] = __builtin_fmaf(-e, dy, acc[1]);
         acc[2] = __builtin_fmaf(-e, dz, acc[2]);
+        acc[3] = __builtin_fmaf(j[3], r3, acc[3]);
         if (MASS) {
-            float gd = j[4] * dx;
-            gd = __builtin_fmaf(j[5], dy, gd);
-            gd = __builtin_fmaf(j[6], dz, gd);
-            const float pr = j[7] * r;
-            acc[3] = __builtin_fmaf(gd, r3, acc[3]);
-            acc[3] = acc[3] + pr;
+            acc[4] = __builtin_fmaf(gd, r3, acc[4]);
+            acc[4] = __builtin_fmaf(j[7], r, acc[4]);
         }
     }
 };
@@ -111,7 +107,7 @@ struct Adjoint {
 // same operation, so d = 0 exactly and the null record adds nothing).
 struct AdjointTile {
     static constexpr int kJWords = 8;
-    static constexpr int kOut = 4;
+    static constexpr int kOut = 5;
     static constexpr int kBlockJ = Adjoint::kBlockJ;
     using Args = VjpTileArgs;
     using IState = Adjoint::IState;
@@ -143,7 +139,7 @@ struct AdjointTile {
     static __device__ __forceinline__ void null_j(float (&r)[8]) { Adjoint::null_j(r); }
     template <bool MASS>
     static __device__ __forceinline__ void pair(const float *j, const IState &k, float eps2,
-                                                float (&acc)[4]) {
+                                                float (&acc)[5]) {
         Adjoint::pair<MASS>(j, k, eps2, acc);
     }
 };

@@ -187,9 +187,9 @@ nbody_status choose_cfg(int kernel, int64_t n, int precision, const nbody_opts &
     return choose_cfg_ij(kernel, n, n, precision, o, cfg, split_ok);
 }
 
-size_t partial_bytes(const TileCfg &c, int precision) {
+size_t partial_bytes(const TileCfg &c, int precision, int outputs) {
     if (c.jl > 1) return 0;  // the split engine keeps its partial sums in registers
-    return align_up((size_t)c.nseg * partial_words(precision) * (size_t)c.npad * 4, 256);
+    return align_up((size_t)c.nseg * partial_words(precision, outputs) * (size_t)c.npad * 4, 256);
 }
 
 nbody_opts resolve_opts(const nbody_opts *opts) {
@@ -224,14 +224,15 @@ nbody_status check_force_f32(int64_t n, const float *pos, const float *mass, flo
     return NBODY_OK;
 }
 
-size_t f64_scratch_bytes(int64_t n, const TileCfg &cfg, int precision) {
-    return partial_bytes(cfg, precision) + align_up(sizeof(float) * 3 * (size_t)n, 256) +
+size_t f64_scratch_bytes(int64_t n, const TileCfg &cfg, int precision, int outputs) {
+    return partial_bytes(cfg, precision, outputs) + align_up(sizeof(float) * 3 * (size_t)n, 256) +
            align_up(centre_scratch_bytes(), 256);
 }
 
-F64Scratch f64_scratch_layout(void *ws, int64_t n, const TileCfg &cfg, int precision) {
+F64Scratch f64_scratch_layout(void *ws, int64_t n, const TileCfg &cfg, int precision,
+                              int outputs) {
     char *base = static_cast<char *>(ws);
-    const size_t pb = partial_bytes(cfg, precision);
+    const size_t pb = partial_bytes(cfg, precision, outputs);
     const size_t xb = align_up(sizeof(float) * 3 * (size_t)n, 256);
     F64Scratch r;
     r.part = base;

@@ -17,8 +17,10 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinalizeArgs a) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int c = blockIdx.y;
     if (i >= a.n) return;
-    ForceOut::put(a, i, c, engine::sum_partial_output<4, MODE, BATCH>(a.part, a.nseg,
-                                                                       (size_t)a.npad, i, c));
+    ForceOut::put(a, i, c, [&](int o) {
+        return engine::sum_partial_output<kForceOutputs, MODE, BATCH>(a.part, a.nseg,
+                                                                      (size_t)a.npad, i, o);
+    });
 }
 
 // Two-stage fixed-order FP64 mean of the positions [3][n]: kCentreBlocks partial

@@ -30,13 +30,19 @@ constexpr int kCentreBlocks = 256;
 // Default number of j's summed in plain FP32 between two compensation / FP64 steps; a
 // pipeline may set its own (Op::kBlockJ), and the engine caps it at the j-tile.  128
 // keeps the two-sums under 0.6 VALU operations per pair for every pipeline (force:
-// 4 outputs, jerk: 7, adjoint: 4).  The FP32 block sum adds at most 127 u sum |term|
+// 4 outputs, jerk: 7, adjoint: 5).  The FP32 block sum adds at most 127 u sum |term|
 // (about sqrt(128) u sum |term| in practice), of the order of the pair rounding.
 constexpr int kBlockJ = 128;
 
-// Words (4-byte) of partial sums written per i-particle and j-segment.
-inline int partial_words(int precision) {
-    return precision == NBODY_PLAIN ? 4 : 8;  // comp: hi[4], lo[4]; fp64red: double[4]
+// Outputs per particle of the force (a, phi) and of the adjoint pipeline (three
+// position sums, the sum that multiplies the particle's own cotangent, the mass sum).
+constexpr int kForceOutputs = 4;
+constexpr int kVjpOutputs = 5;
+
+// Words (4-byte) of partial sums written per i-particle and j-segment for `outputs`
+// outputs (compensated: hi and lo; FP64-reduced: one double).
+inline int partial_words(int precision, int outputs = kForceOutputs) {
+    return precision == NBODY_PLAIN ? outputs : 2 * outputs;
 }
 
 // Shape of one force launch.
@@ -221,6 +227,7 @@ struct VjpFinalizeArgs {
     double *grad_pos;   // [3][n]
     double *grad_mass;  // [n] or nullptr
     int accumulate;     // 1: add into grad_pos / grad_mass instead of overwriting
+    const double *ga;   // dL/da [3][n]: the particle's own cotangent (its FP32 value is used)
 };
 
 // Thread-local error reporting.
@@ -249,7 +256,7 @@ nbody_status choose_cfg(int kernel, int64_t n, int precision, const nbody_opts &
 // The same for ni i-particles against nj j-particles (nj >= 1).
 nbody_status choose_cfg_ij(int kernel, int64_t ni, int64_t nj, int precision, const nbody_opts &o,
                            TileCfg *cfg, bool split_ok);
-size_t partial_bytes(const TileCfg &c, int precision);
+size_t partial_bytes(const TileCfg &c, int precision, int outputs = kForceOutputs);
 size_t align_up(size_t v, size_t a);
 nbody_status check_common(int64_t n, const void *pos, const void *mass, float eps,
                           const void *acc, const nbody_opts &o);
@@ -271,8 +278,10 @@ struct F64Scratch {
     float *x32;
     double *centre_scratch;
 };
-size_t f64_scratch_bytes(int64_t n, const TileCfg &cfg, int precision);
-F64Scratch f64_scratch_layout(void *ws, int64_t n, const TileCfg &cfg, int precision);
+size_t f64_scratch_bytes(int64_t n, const TileCfg &cfg, int precision,
+                         int outputs = kForceOutputs);
+F64Scratch f64_scratch_layout(void *ws, int64_t n, const TileCfg &cfg, int precision,
+                              int outputs = kForceOutputs);
 
 // One force evaluation from FP64 positions: centre + conversion (per opts.centre),
 // pair kernel, FP64 finalize (optionally followed by v += kick_h * a).

@@ -17,15 +17,20 @@
 //     permutations and row mirrors for lane distances 1 to 8, v_permlane16_swap and
 //     v_permlane32_swap for 16 and 32.  Both lanes of every exchange add the same two
 //     values, so all Q lanes end with bitwise the same sum, and the order is fixed;
-//   * the group's lanes then store the outputs through a Sink (lane q stores the
-//     outputs c with c % Q == q), which also applies what the FP64 finalize of the tile
-//     engine applies (self potential, a fused leapfrog kick, accumulation).
+//   * the group's lanes then store the results through a Sink (lane q stores the slots
+//     c with c % Q == q), which also applies what the FP64 finalize of the tile engine
+//     applies (self potential, a fused leapfrog kick, the adjoint's own-cotangent term,
+//     accumulation).
 // No partial sums leave the chip and no second launch is needed; results are bitwise
 // reproducible for a given launch shape (IPL, Q, JT).
 //
 // A Sink provides
 //   struct Args;
-//   static void put(const Args&, int i, int c, double r);  // output c of i-particle i
+//   static constexpr int kOutputs;          // the pipeline's outputs it reads
+//   static constexpr int stores(bool full);  // store slots per particle
+//   template <class Sum> static void put(const Args&, int i, int c, Sum sum);
+//                                           // slot c of i-particle i; sum(o) is the FP64
+//                                           // sum of output o
 #pragma once
 
 #include "tile_engine.h"
@@ -277,22 +282,27 @@ __global__ __launch_bounds__(kTPB) void split_kernel(typename Op::Args a, typena
         __syncthreads();
     }
 
-    // Cross-lane sums of each (i, output) and the stores.
+    // Cross-lane sums of each (i, output), then the stores: lane q of a group stores the
+    // slots c with c % Q == q (every lane of the group holds every sum).
+    static_assert(Sink::kOutputs == NO, "the output stage reads the pipeline's outputs");
 #pragma unroll
     for (int k = 0; k < IPL; ++k) {
+        double rr[NO];
 #pragma unroll
         for (int c = 0; c < NO; ++c) {
+            rr[c] = 0.0;
             if (!FULL && c == NO - 1) continue;
-            double r;
             if constexpr (MODE == NBODY_PLAIN) {
-                r = (double)group_sum<Q>(hs[k][c]);
+                rr[c] = (double)group_sum<Q>(hs[k][c]);
             } else if constexpr (MODE == NBODY_COMP) {
-                r = group_sum<Q>((double)hs[k][c] + (double)ls[k][c]);
+                rr[c] = group_sum<Q>((double)hs[k][c] + (double)ls[k][c]);
             } else {
-                r = group_sum<Q>(ds[k][c]);
+                rr[c] = group_sum<Q>(ds[k][c]);
             }
-            if (c % Q == q && own[k] < ni) Sink::put(f, own[k], c, r);
         }
+#pragma unroll
+        for (int c = 0; c < Sink::stores(FULL); ++c)
+            if (c % Q == q && own[k] < ni) Sink::put(f, own[k], c, [&](int o) { return rr[o]; });
     }
 }
 

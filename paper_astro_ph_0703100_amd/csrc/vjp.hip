@@ -6,16 +6,19 @@
 namespace nbody {
 namespace {
 
-// One thread per (particle, output), as in the force finalize: fixed-order sums of the
-// segment partials (which hold no j == k term), then dL/dx_k (outputs 0-2) or dL/dm_k
-// (output 3, the negated sum).  Grid: (ceil(n / 256), 4 outputs, or 3 without dL/dm).
+// One thread per (particle, store slot), as in the force finalize: fixed-order sums of
+// the segment partials (which hold no j == k term), then dL/dx_k (slots 0-2, from the
+// slot's own sum and the sum B_k) or dL/dm_k (slot 3, the negated mass sum).  Grid:
+// (ceil(n / 256), 4 slots, or 3 without dL/dm).
 template <int MODE, int BATCH>
 __global__ __launch_bounds__(256) void vjp_finalize_kernel(VjpFinalizeArgs a) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     const int c = blockIdx.y;
     if (k >= a.n) return;
-    VjpOut::put(a, k, c, engine::sum_partial_output<4, MODE, BATCH>(a.part, a.nseg,
-                                                                      (size_t)a.npad, k, c));
+    VjpOut::put(a, k, c, [&](int o) {
+        return engine::sum_partial_output<kVjpOutputs, MODE, BATCH>(a.part, a.nseg,
+                                                                    (size_t)a.npad, k, o);
+    });
 }
 
 }  // namespace
