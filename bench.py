@@ -436,7 +436,7 @@ def bench_small(args, torch, w):
                           "acc": graph_res[0], "pot": graph_res[1]}
         del graph
         print("bench: %-8s N=%d  %.2f us per evaluation in a graph, %.2f us eager (shape "
-              "ipl %d jtile %d nseg %d jlanes %d)" % ((precision, n, kernel_ms * 1e3,
+              "ipl %d jtile %d nseg %d jlanes %d symmetric %d)" % ((precision, n, kernel_ms * 1e3,
                                                        eager_ms * 1e3) + tuple(shape)),
               file=sys.stderr, flush=True)
     # The launch floor: the same graph of evaluations of a one-particle system (one block,
@@ -480,7 +480,7 @@ def bench_small(args, torch, w):
         "launch_floor_ms": floor_ms,
         "cpu_baseline": cpu,
         "modes": {q: {"ms_per_step": r["kernel_ms"], "eager_ms_per_call": r["eager_ms"],
-                      "shape": dict(zip(("ipl", "jtile", "nseg", "jlanes"), r["shape"])),
+                      "shape": dict(zip(("ipl", "jtile", "nseg", "jlanes", "symmetric"), r["shape"])),
                       **fractions("gravity", pairs, r["kernel_ms"]),
                       "errors": errors.get(q)} for q, r in res.items()},
     }

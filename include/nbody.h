@@ -84,11 +84,12 @@ typedef struct nbody_opts {
     int32_t jtile;      /* j-particles per LDS tile: 64, 128, 256, 512; 0 = default   */
     int32_t nseg;       /* j-segments per i-tile (grid y), <= 1024; 0 = chosen from n */
     int32_t jlanes;     /* lanes that share one i-particle's j-range (see below)       */
+    int32_t symmetric;  /* 0: tuned; 1: off; 2: each unordered pair once (see below)   */
     void *workspace;    /* device scratch, or NULL for the library's per-device cache */
     size_t workspace_bytes;
 } nbody_opts;
 
-/* Launch shapes.  Two pair engines evaluate the same sums:
+/* Launch shapes.  Three pair engines evaluate the same sums:
  *   - the grid engine (jlanes = 1): a block of 256 lanes holds 256 * ipl i-particles
  *     and walks one of nseg j-segments in LDS tiles of jtile records (64 to 512);
  *     the segment partial sums go to scratch memory and a second kernel adds them
@@ -101,10 +102,21 @@ typedef struct nbody_opts {
  *     in FP64 (PLAIN: FP32) by DPP / permlane moves in a fixed order.  One launch, no
  *     scratch for partial sums.  Available for nbody_force, nbody_force_ex,
  *     nbody_force_f64, the leapfrog, nbody_force_vjp(_f64) and the leapfrog adjoint,
- *     not with NBODY_CENTRE_TILE (which uses the grid engine's i-tiles).
- * jlanes = 0 with ipl, jtile and nseg all 0 takes the shape from the tuning table
- * (either engine); jlanes = 0 with any of them set selects the grid engine.  Results
- * are bitwise reproducible for a given shape; different shapes round differently. */
+ *     not with NBODY_CENTRE_TILE (which uses the grid engine's i-tiles);
+ *   - the symmetric engine (symmetric = 2; ipl = 1, 2 or 4; jtile = 64 or 128;
+ *     jlanes 0 or 1): the pair term of eq. (1) is antisymmetric, so each unordered
+ *     pair {i, j} is evaluated once and its term added to both particles.  Block rows
+ *     of 512 * ipl particles take the pairs with every later particle, in work items
+ *     of a few j-tiles (nseg: items in the longest row, 0 = chosen from n); the i-side
+ *     sums are accumulated as in the grid engine, the j-side sums per wavefront (FP32,
+ *     64 * ipl terms) and over the block's 8 wavefronts in FP64 (PLAIN: FP32), and a
+ *     second kernel adds both per particle in a fixed order.  Scratch grows as
+ *     n^2 / (512 * ipl) words.  Available for nbody_force, nbody_force_ex,
+ *     nbody_force_f64 and the leapfrog, not with NBODY_CENTRE_TILE.
+ * jlanes = 0 and symmetric = 0 with ipl, jtile and nseg all 0 take the shape from the
+ * tuning table (any engine); with any of them set the grid engine is used unless
+ * jlanes > 1 or symmetric = 2 selects another.  Results are bitwise reproducible for
+ * a given shape; different shapes round differently. */
 
 /* Fills *opts with the defaults (NBODY_COMP, NBODY_CENTRE_SYSTEM, self excluded,
  * tile shape from the tuning table, library workspace). */
@@ -414,10 +426,12 @@ NBODY_API nbody_status nbody_graph_create_leapfrog_batched(const nbody_plan *pla
 #define NBODY_KERNEL_BATCHED 2
 #define NBODY_KERNEL_JERK 3
 NBODY_API nbody_status nbody_tune_set(int32_t kernel, int32_t precision, int64_t n, int32_t ipl,
-                                      int32_t jtile, int32_t nseg, int32_t jlanes);
-/* shape[0..4) = ipl, jtile, nseg, jlanes in effect for (kernel, precision, n)
- * (jlanes 1: grid engine; 8 to 64: split engine, only for NBODY_KERNEL_FORCE and
- * NBODY_KERNEL_VJP). */
+                                      int32_t jtile, int32_t nseg, int32_t jlanes,
+                                      int32_t symmetric);
+/* shape[0..5) = ipl, jtile, nseg, jlanes, symmetric in effect for (kernel, precision,
+ * n) (jlanes 1: grid engine; 8 to 64: split engine, only for NBODY_KERNEL_FORCE and
+ * NBODY_KERNEL_VJP; symmetric 1: symmetric engine, only for NBODY_KERNEL_FORCE, with
+ * jlanes 1).  shape must hold 5 values. */
 NBODY_API nbody_status nbody_tune_get(int32_t kernel, int32_t precision, int64_t n,
                                       int32_t *shape);
 NBODY_API nbody_status nbody_tune_load(const char *path);

@@ -47,6 +47,7 @@ class nbody_opts(ctypes.Structure):
         ("jtile", ctypes.c_int32),
         ("nseg", ctypes.c_int32),
         ("jlanes", ctypes.c_int32),
+        ("symmetric", ctypes.c_int32),
         ("workspace", ctypes.c_void_p),
         ("workspace_bytes", ctypes.c_size_t),
     ]
@@ -110,7 +111,7 @@ SIGNATURES = {
     "nbody_graph_create_leapfrog_batched": (_I32, [_P, _P, _P, _P, _P, _D, _I32, _P, _P, _P,
                                                    ctypes.POINTER(_P)]),
     "nbody_morton_order": (_I32, [_I64, _P, _P, _P]),
-    "nbody_tune_set": (_I32, [_I32, _I32, _I64, _I32, _I32, _I32, _I32]),
+    "nbody_tune_set": (_I32, [_I32, _I32, _I64, _I32, _I32, _I32, _I32, _I32]),
     "nbody_tune_get": (_I32, [_I32, _I32, _I64, ctypes.POINTER(_I32)]),
     "nbody_tune_load": (_I32, [ctypes.c_char_p]),
     "nbody_tune_save": (_I32, [ctypes.c_char_p]),
@@ -362,16 +363,16 @@ def nbody_graph_create_leapfrog_batched(plan, pos64, vel64, mass, eps, dt, nstep
     return h.value
 
 
-def nbody_tune_set(kernel, precision, n, ipl, jtile, nseg, jlanes=1):
-    return _check(load().nbody_tune_set(kernel, precision, n, ipl, jtile, nseg, jlanes),
+def nbody_tune_set(kernel, precision, n, ipl, jtile, nseg, jlanes=1, symmetric=0):
+    return _check(load().nbody_tune_set(kernel, precision, n, ipl, jtile, nseg, jlanes, symmetric),
                   "nbody_tune_set")
 
 
 def nbody_tune_get(kernel, precision, n):
-    """(ipl, jtile, nseg, jlanes) in effect for (kernel, precision, n)."""
-    shape = (_I32 * 4)()
+    """(ipl, jtile, nseg, jlanes, symmetric) in effect for (kernel, precision, n)."""
+    shape = (_I32 * 5)()
     _check(load().nbody_tune_get(kernel, precision, n, shape), "nbody_tune_get")
-    return int(shape[0]), int(shape[1]), int(shape[2]), int(shape[3])
+    return tuple(int(v) for v in shape)
 
 
 def nbody_tune_load(path):

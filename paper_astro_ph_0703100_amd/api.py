@@ -17,12 +17,13 @@ __all__ = ["make_opts", "force", "force_f64", "leapfrog", "LeapfrogGraph", "Batc
 
 def make_opts(precision: str = "comp", centre: str = "system", self_pot: bool = False,
               ipl: int = 0, jtile: int = 0, nseg: int = 0, jlanes: int = 0,
-              workspace: torch.Tensor | None = None):
+              symmetric: int = 0, workspace: torch.Tensor | None = None):
     o = _lib.nbody_opts_default()
     o.precision = _lib.PRECISIONS[precision]
     o.centre = _lib.CENTRES[centre]
     o.self_pot = int(bool(self_pot))
     o.ipl, o.jtile, o.nseg, o.jlanes = int(ipl), int(jtile), int(nseg), int(jlanes)
+    o.symmetric = int(symmetric)
     if workspace is not None:
         o.workspace = workspace.data_ptr()
         o.workspace_bytes = workspace.numel() * workspace.element_size()

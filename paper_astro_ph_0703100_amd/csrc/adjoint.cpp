@@ -84,7 +84,7 @@ size_t nbody_workspace_size_vjp(int64_t n, const nbody_opts *opts) {
     nbody_opts o = resolve_opts(opts);
     if (n <= 0) return 0;
     TileCfg c;
-    if (choose_cfg(KERNEL_VJP, n, o.precision, o, &c, o.centre != NBODY_CENTRE_TILE) != NBODY_OK) return 0;
+    if (choose_cfg(KERNEL_VJP, n, o.precision, o, &c, o.centre != NBODY_CENTRE_TILE ? kEngineSplit : 0) != NBODY_OK) return 0;
     return vjp_f64_bytes(n, c, o.precision);
 }
 
@@ -104,7 +104,7 @@ nbody_status nbody_force_vjp(int64_t n, const float *pos, const float *mass, flo
     if (n == 0) return NBODY_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
     TileCfg cfg;
-    if ((st = choose_cfg(KERNEL_VJP, n, o.precision, o, &cfg, true))) return st;
+    if ((st = choose_cfg(KERNEL_VJP, n, o.precision, o, &cfg, kEngineSplit))) return st;
     void *ws = nullptr;
     if ((st = get_workspace(o, partial_bytes(cfg, o.precision, kVjpOutputs), s, &ws))) return st;
     return vjp_f32_core(n, pos, mass, eps, g_acc, g_pot, grad_pos, grad_mass, false, o, cfg, ws, s);
@@ -121,7 +121,7 @@ nbody_status nbody_force_vjp_f64(int64_t n, const double *pos64, const float *ma
     if (n == 0) return NBODY_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
     TileCfg cfg;
-    if ((st = choose_cfg(KERNEL_VJP, n, o.precision, o, &cfg, o.centre != NBODY_CENTRE_TILE))) return st;
+    if ((st = choose_cfg(KERNEL_VJP, n, o.precision, o, &cfg, o.centre != NBODY_CENTRE_TILE ? kEngineSplit : 0))) return st;
     void *ws = nullptr;
     if ((st = get_workspace(o, vjp_f64_bytes(n, cfg, o.precision), s, &ws))) return st;
     return vjp_f64_core(n, pos64, mass, eps, g_acc, g_pot, grad_pos, grad_mass, false, o, cfg,
@@ -146,7 +146,7 @@ nbody_status nbody_leapfrog_adjoint(int64_t n, const double *traj, const float *
     if (n == 0 || nsteps == 0) return NBODY_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
     TileCfg cfg;
-    if ((st = choose_cfg(KERNEL_VJP, n, o.precision, o, &cfg, o.centre != NBODY_CENTRE_TILE))) return st;
+    if ((st = choose_cfg(KERNEL_VJP, n, o.precision, o, &cfg, o.centre != NBODY_CENTRE_TILE ? kEngineSplit : 0))) return st;
     const size_t base = vjp_f64_bytes(n, cfg, o.precision);
     const size_t n3 = 3 * (size_t)n;
     void *ws = nullptr;

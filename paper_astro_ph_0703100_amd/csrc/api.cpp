@@ -115,19 +115,67 @@ nbody_status get_workspace(const nbody_opts &o, size_t need, hipStream_t s, void
 // Launch shape for ni i-particles against nj j-particles: explicit options first, then
 // the tuning table (its j-split only when the two sets have the same size, the shape it
 // was measured on), then a default that gives every compute unit several blocks.
-// split_ok: the caller has a split-engine kernel for this evaluation (single-set force
-// or adjoint without per-i-tile centres); otherwise the grid engine is used.
+// engines (kEngine* bits): the engines besides the grid engine that the caller has
+// kernels for (split: single-set force or adjoint without per-i-tile centres;
+// symmetric: single-set force on FP32 or system-centred positions).
 nbody_status choose_cfg_ij(int kernel, int64_t ni, int64_t nj, int precision, const nbody_opts &o,
-                           TileCfg *cfg, bool split_ok) {
+                           TileCfg *cfg, int engines) {
     TileCfg c;
     if (o.jlanes < 0) return set_error(NBODY_EINVAL, "jlanes must be >= 0");
-    if (o.jlanes > 1 && !split_ok)
+    if (o.symmetric < 0 || o.symmetric > 2)
+        return set_error(NBODY_EINVAL, "symmetric must be 0 (tuned), 1 (off) or 2 (on)");
+    if (o.jlanes > 1 && !(engines & kEngineSplit))
         return set_error(NBODY_EUNSUPPORTED,
                          "jlanes > 1 (split engine) is available for the single-set force and "
                          "adjoint without per-i-tile centres only");
+    if (o.symmetric == 2 && !(engines & kEngineSym))
+        return set_error(NBODY_EUNSUPPORTED,
+                         "symmetric = 2 (symmetric engine) is available for the single-set force "
+                         "on FP32 or system-centred positions only");
+    if (o.symmetric == 2 && o.jlanes > 1)
+        return set_error(NBODY_EINVAL, "the symmetric engine takes jlanes 0 or 1");
     const bool explicit_shape = o.ipl || o.jtile || o.nseg;
-    TuneEntry t = tuned_shape(kernel, precision, nj, split_ok);
-    const int jl = o.jlanes ? o.jlanes : (explicit_shape ? 1 : t.jl);
+    TuneEntry t = tuned_shape(kernel, precision, nj, engines);
+    const bool use_sym = ni == nj && (o.symmetric == 2 ||
+                                      (o.symmetric == 0 && !o.jlanes && !explicit_shape && t.sym));
+    if (use_sym) {
+        const TuneEntry e{o.ipl ? o.ipl : (t.sym ? t.ipl : 4), o.jtile ? o.jtile : (t.sym ? t.jt : 64),
+                          o.nseg ? o.nseg : (t.sym ? t.nseg : 0), 1, 1};
+        if (!valid_shape(kernel, e))
+            return set_error(NBODY_EINVAL,
+                             "symmetric-engine shape needs ipl in {1, 2, 4}, jtile in {64, 128} "
+                             "and nseg in [0, " + std::to_string(kMaxSeg) + "]");
+        const int bi = 64 * kSymWaves * e.ipl;
+        const int n = (int)ni;
+        c.sym = 1;
+        c.ipl = e.ipl;
+        c.jt = e.jt;
+        c.jl = 1;
+        c.nb = (int)((ni + bi - 1) / bi);
+        c.npad = c.nb * bi;
+        const int64_t t0 = sym::row_tiles(n, bi, c.jt, 0);
+        int64_t segt;
+        if (e.nseg > 0) {
+            segt = (t0 + e.nseg - 1) / e.nseg;
+        } else {
+            // About 16 work items per compute unit (4 resident blocks of 8 waves each, so
+            // 4 rounds), each a whole number of j-tiles.
+            int64_t all = 0;
+            for (int b = 0; b < c.nb; ++b) all += sym::row_tiles(n, bi, c.jt, b);
+            segt = all / ((int64_t)device_info().cus * 16);
+        }
+        c.segt = (int)std::max<int64_t>(1, segt);
+        c.nseg = sym::row_segments(n, bi, c.jt, c.segt, 0);
+        int64_t items = 0;
+        for (int s = 0; s < c.nseg; ++s) items += sym::items_of_segment(n, bi, c.jt, c.segt, c.nb, s);
+        c.nitems = (int)items;
+        c.itiles = 0;
+        c.seg_len = 0;
+        *cfg = c;
+        return NBODY_OK;
+    }
+    const bool split_ok = (engines & kEngineSplit) != 0;
+    const int jl = o.jlanes ? o.jlanes : (explicit_shape || o.symmetric == 2 ? 1 : t.jl);
     if (jl > 1) {
         // Split engine: one launch of ceil(ni / i-per-block) blocks, no j-segments.
         const bool from_table = t.jl > 1;
@@ -148,6 +196,8 @@ nbody_status choose_cfg_ij(int kernel, int64_t ni, int64_t nj, int precision, co
         *cfg = c;
         return NBODY_OK;
     }
+    (void)split_ok;
+    if (t.jl > 1 || t.sym) t = TuneEntry{1, 256, 0, 1};  // the table's shape is another engine's
     if (t.jl > 1) t = TuneEntry{1, 256, 0, 1};  // the table's split shape does not apply
     c.ipl = o.ipl ? o.ipl : t.ipl;
     c.jt = o.jtile ? o.jtile : t.jt;
@@ -183,12 +233,13 @@ nbody_status choose_cfg_ij(int kernel, int64_t ni, int64_t nj, int precision, co
 }
 
 nbody_status choose_cfg(int kernel, int64_t n, int precision, const nbody_opts &o, TileCfg *cfg,
-                        bool split_ok) {
-    return choose_cfg_ij(kernel, n, n, precision, o, cfg, split_ok);
+                        int engines) {
+    return choose_cfg_ij(kernel, n, n, precision, o, cfg, engines);
 }
 
 size_t partial_bytes(const TileCfg &c, int precision, int outputs) {
     if (c.jl > 1) return 0;  // the split engine keeps its partial sums in registers
+    if (c.sym) return sym_ipart_bytes(c, precision) + sym_jpart_bytes(c, precision);
     return align_up((size_t)c.nseg * partial_words(precision, outputs) * (size_t)c.npad * 4, 256);
 }
 
@@ -250,6 +301,7 @@ nbody_status force_f32_core(int64_t n, const float *pos, const float *mass, floa
     FinalizeArgs fa{ws, cfg.nseg, cfg.npad, (int)n, mass, eps, o.self_pot, acc, pot, kick_v,
                     kick_h};
     if (cfg.jl > 1) return launch_pair_split(cfg, o.precision, pot != nullptr, pa, fa, s);
+    if (cfg.sym) return launch_pair_sym(cfg, o.precision, pot != nullptr, pa, fa, s);
     nbody_status st = launch_pair(cfg, o.precision, pot != nullptr, pa, s);
     if (st) return st;
     return launch_finalize(o.precision, fa, s);
@@ -308,7 +360,7 @@ size_t nbody_workspace_size(int64_t n, const nbody_opts *opts) {
     if (opts) o = *opts;
     if (n <= 0) return 0;
     TileCfg c;
-    if (choose_cfg(KERNEL_FORCE, n, o.precision, o, &c, o.centre != NBODY_CENTRE_TILE) != NBODY_OK)
+    if (choose_cfg(KERNEL_FORCE, n, o.precision, o, &c, force_engines(o)) != NBODY_OK)
         return 0;
     return f64_scratch_bytes(n, c, o.precision);
 }
@@ -322,7 +374,7 @@ nbody_status nbody_force_ex(int64_t n, const float *pos, const float *mass, floa
     if (n == 0) return NBODY_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
     TileCfg cfg;
-    if ((st = choose_cfg(KERNEL_FORCE, n, o.precision, o, &cfg, true))) return st;
+    if ((st = choose_cfg(KERNEL_FORCE, n, o.precision, o, &cfg, kEngineSplit | kEngineSym))) return st;
     void *ws = nullptr;
     if ((st = get_workspace(o, partial_bytes(cfg, o.precision), s, &ws))) return st;
     return force_f32_core(n, pos, mass, eps, acc, pot, o, cfg, ws, nullptr, 0.0, s);
@@ -344,7 +396,7 @@ nbody_status nbody_force_f64(int64_t n, const double *pos64, const float *mass, 
     if (n == 0) return NBODY_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
     TileCfg cfg;
-    if ((st = choose_cfg(KERNEL_FORCE, n, o.precision, o, &cfg, o.centre != NBODY_CENTRE_TILE))) return st;
+    if ((st = choose_cfg(KERNEL_FORCE, n, o.precision, o, &cfg, force_engines(o)))) return st;
     void *ws = nullptr;
     if ((st = get_workspace(o, f64_scratch_bytes(n, cfg, o.precision), s, &ws))) return st;
     return force_f64_core(n, pos64, mass, eps, acc, pot, o, cfg,
@@ -377,7 +429,7 @@ nbody_status nbody_force_ij(int64_t ni, const float *pos_i, const float *eps_i, 
         return pot ? launch_fill_f64(ni, pot, 0.0, s) : NBODY_OK;
     }
     TileCfg cfg;
-    if ((st = choose_cfg_ij(KERNEL_FORCE, ni, nj, o.precision, o, &cfg, false))) return st;
+    if ((st = choose_cfg_ij(KERNEL_FORCE, ni, nj, o.precision, o, &cfg, 0))) return st;
     void *ws = nullptr;
     if ((st = get_workspace(o, partial_bytes(cfg, o.precision), s, &ws))) return st;
     IJPairArgs a{pos_i, pos_i + ni, pos_i + 2 * ni, eps_i, pos_j, pos_j + nj, pos_j + 2 * nj,
@@ -391,7 +443,7 @@ size_t nbody_workspace_size_ij(int64_t ni, int64_t nj, const nbody_opts *opts) {
     nbody_opts o = resolve_opts(opts);
     if (ni <= 0 || nj <= 0) return 0;
     TileCfg c;
-    if (choose_cfg_ij(KERNEL_FORCE, ni, nj, o.precision, o, &c, false) != NBODY_OK) return 0;
+    if (choose_cfg_ij(KERNEL_FORCE, ni, nj, o.precision, o, &c, 0) != NBODY_OK) return 0;
     return partial_bytes(c, o.precision);
 }
 

@@ -160,6 +160,10 @@ nbody_status nbody_plan_create_batched(int32_t nsys, const int64_t *h_offsets,
     if (o.workspace) return set_error(NBODY_EINVAL, "a plan owns its scratch; opts->workspace must be NULL");
     if (o.jlanes > 1) return set_error(NBODY_EUNSUPPORTED, "batched plans use the grid engine (jlanes 0 or 1)");
     if (o.jlanes < 0) return set_error(NBODY_EINVAL, "jlanes must be >= 0");
+    if (o.symmetric < 0 || o.symmetric > 2)
+        return set_error(NBODY_EINVAL, "symmetric must be 0 (tuned), 1 (off) or 2 (on)");
+    if (o.symmetric == 2)
+        return set_error(NBODY_EUNSUPPORTED, "batched plans use the grid engine (symmetric 0 or 1)");
     if (nsys > 0 && h_offsets[0] != 0) return set_error(NBODY_EINVAL, "offsets[0] must be 0");
     for (int32_t k = 0; k < nsys; ++k)
         if (h_offsets[k + 1] < h_offsets[k])
@@ -167,7 +171,7 @@ nbody_status nbody_plan_create_batched(int32_t nsys, const int64_t *h_offsets,
     const int64_t total = nsys > 0 ? h_offsets[nsys] : 0;
     if (total > INT32_MAX / 2) return set_error(NBODY_EINVAL, "total particles must be < 2^30");
 
-    TuneEntry te = tuned_shape(KERNEL_BATCHED, o.precision, total / std::max<int64_t>(1, nsys), false);
+    TuneEntry te = tuned_shape(KERNEL_BATCHED, o.precision, total / std::max<int64_t>(1, nsys), 0);
     const int ipl = o.ipl ? o.ipl : te.ipl;
     const int jt = o.jtile ? o.jtile : te.jt;
     if (!(ipl == 1 || ipl == 2 || ipl == 4 || ipl == 8))

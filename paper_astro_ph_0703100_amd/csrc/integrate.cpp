@@ -101,7 +101,7 @@ nbody_status nbody_leapfrog(int64_t n, double *pos64, double *vel64, const float
     if (n == 0) return NBODY_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
     TileCfg cfg;
-    if ((st = choose_cfg(KERNEL_FORCE, n, o.precision, o, &cfg, o.centre != NBODY_CENTRE_TILE))) return st;
+    if ((st = choose_cfg(KERNEL_FORCE, n, o.precision, o, &cfg, force_engines(o)))) return st;
     void *ws = nullptr;
     if ((st = get_workspace(o, f64_scratch_bytes(n, cfg, o.precision), s, &ws))) return st;
     return enqueue_steps(n, pos64, vel64, mass, eps, dt, nsteps, acc, pot, traj,
@@ -123,7 +123,7 @@ nbody_status nbody_graph_create_leapfrog(int64_t n, double *pos64, double *vel64
     hipStream_t user = static_cast<hipStream_t>(stream);
     if (stream_capturing(user)) return set_error(NBODY_ECAPTURE, "stream is already capturing");
     TileCfg cfg;
-    if ((st = choose_cfg(KERNEL_FORCE, n, o.precision, o, &cfg, o.centre != NBODY_CENTRE_TILE))) return st;
+    if ((st = choose_cfg(KERNEL_FORCE, n, o.precision, o, &cfg, force_engines(o)))) return st;
 
     nbody_graph *g = new (std::nothrow) nbody_graph;
     if (!g) return set_error(NBODY_ENOMEM, "out of host memory");

@@ -162,7 +162,7 @@ size_t nbody_workspace_size_jerk(int64_t n, const nbody_opts *opts) {
     nbody_opts o = resolve_opts(opts);
     if (n <= 0) return 0;
     TileCfg c;
-    if (choose_cfg(KERNEL_JERK, n, o.precision, o, &c, false) != NBODY_OK) return 0;
+    if (choose_cfg(KERNEL_JERK, n, o.precision, o, &c, 0) != NBODY_OK) return 0;
     return jerk_f64_bytes(n, c, o.precision);
 }
 
@@ -179,7 +179,7 @@ nbody_status nbody_force_jerk(int64_t n, const float *pos, const float *vel, con
     if (n == 0) return NBODY_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
     TileCfg cfg;
-    if ((st = choose_cfg(KERNEL_JERK, n, o.precision, o, &cfg, false))) return st;
+    if ((st = choose_cfg(KERNEL_JERK, n, o.precision, o, &cfg, 0))) return st;
     void *ws = nullptr;
     if ((st = get_workspace(o, jerk_partial_bytes(cfg, o.precision), s, &ws))) return st;
     return jerk_core(n, pos, vel, mass, eps, acc, jerk, pot, o, cfg, ws, s);
@@ -198,7 +198,7 @@ nbody_status nbody_force_jerk_f64(int64_t n, const double *pos64, const double *
     if (n == 0) return NBODY_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
     TileCfg cfg;
-    if ((st = choose_cfg(KERNEL_JERK, n, o.precision, o, &cfg, false))) return st;
+    if ((st = choose_cfg(KERNEL_JERK, n, o.precision, o, &cfg, 0))) return st;
     void *ws = nullptr;
     if ((st = get_workspace(o, jerk_f64_bytes(n, cfg, o.precision), s, &ws))) return st;
     return jerk_f64_core(n, pos64, vel64, mass, eps, acc, jerk, pot, o, cfg,
@@ -234,7 +234,7 @@ nbody_status nbody_force_jerk_ij(int64_t ni, const float *pos_i, const float *ve
         return pot ? launch_fill_f64(ni, pot, 0.0, s) : NBODY_OK;
     }
     TileCfg cfg;
-    if ((st = choose_cfg_ij(KERNEL_JERK, ni, nj, o.precision, o, &cfg, false))) return st;
+    if ((st = choose_cfg_ij(KERNEL_JERK, ni, nj, o.precision, o, &cfg, 0))) return st;
     void *ws = nullptr;
     if ((st = get_workspace(o, jerk_partial_bytes(cfg, o.precision), s, &ws))) return st;
     JerkIJArgs a{pos_i, pos_i + ni, pos_i + 2 * ni, vel_i, vel_i + ni, vel_i + 2 * ni,
@@ -249,7 +249,7 @@ size_t nbody_workspace_size_jerk_ij(int64_t ni, int64_t nj, const nbody_opts *op
     nbody_opts o = resolve_opts(opts);
     if (ni <= 0 || nj <= 0) return 0;
     TileCfg c;
-    if (choose_cfg_ij(KERNEL_JERK, ni, nj, o.precision, o, &c, false) != NBODY_OK) return 0;
+    if (choose_cfg_ij(KERNEL_JERK, ni, nj, o.precision, o, &c, 0) != NBODY_OK) return 0;
     return jerk_partial_bytes(c, o.precision);
 }
 
@@ -257,7 +257,7 @@ size_t nbody_workspace_size_hermite(int64_t n, const nbody_opts *opts) {
     nbody_opts o = resolve_opts(opts);
     if (n <= 0) return 0;
     TileCfg c;
-    if (choose_cfg(KERNEL_JERK, n, o.precision, o, &c, false) != NBODY_OK) return 0;
+    if (choose_cfg(KERNEL_JERK, n, o.precision, o, &c, 0) != NBODY_OK) return 0;
     return hermite_bytes(n, c, o.precision);
 }
 
@@ -272,7 +272,7 @@ nbody_status nbody_hermite(int64_t n, double *pos64, double *vel64, const float 
     if (n == 0) return NBODY_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
     TileCfg cfg;
-    if ((st = choose_cfg(KERNEL_JERK, n, o.precision, o, &cfg, false))) return st;
+    if ((st = choose_cfg(KERNEL_JERK, n, o.precision, o, &cfg, 0))) return st;
     void *ws = nullptr;
     if ((st = get_workspace(o, hermite_bytes(n, cfg, o.precision), s, &ws))) return st;
     return enqueue_hermite(n, pos64, vel64, mass, eps, dt, nsteps, acc, jerk,
@@ -294,7 +294,7 @@ nbody_status nbody_graph_create_hermite(int64_t n, double *pos64, double *vel64,
     hipStream_t user = static_cast<hipStream_t>(stream);
     if (stream_capturing(user)) return set_error(NBODY_ECAPTURE, "stream is already capturing");
     TileCfg cfg;
-    if ((st = choose_cfg(KERNEL_JERK, n, o.precision, o, &cfg, false))) return st;
+    if ((st = choose_cfg(KERNEL_JERK, n, o.precision, o, &cfg, 0))) return st;
     nbody_graph *g = new (std::nothrow) nbody_graph;
     if (!g) return set_error(NBODY_ENOMEM, "out of host memory");
     auto fail = [&](nbody_status code) {

@@ -9,6 +9,7 @@
 #include <string>
 
 #include "nbody.h"
+#include "tuning.h"
 
 // A captured HIP graph and the scratch memory it owns (if any).
 struct nbody_graph {
@@ -55,7 +56,43 @@ struct TileCfg {
     int npad = 0;    // itiles * kTPB * ipl
     int jl = 1;      // lanes per i-particle's j-range: 1 = grid engine, 8..64 = split engine
                      // (then itiles = blocks of 4 * (64 / jl) * ipl i's, nseg = 1)
+    // Symmetric engine (sym = 1; jl = 1): block rows of 512 * ipl particles, nb rows,
+    // segt j-tiles per work item, nitems work items (the grid), smax segments in row 0
+    // (nseg = smax), npad = nb * 512 * ipl.
+    int sym = 0;
+    int segt = 0;
+    int nb = 0;
+    int nitems = 0;
 };
+
+// Waves per block of the symmetric engine.
+constexpr int kSymWaves = 8;
+
+namespace sym {
+
+// Work items of segment s: every row for s = 0 (each has its diagonal), else the rows
+// whose symmetric range has more than s * segt tiles.
+__host__ __device__ inline int items_of_segment(int n, int bi, int jt, int segt, int nb, int s) {
+    if (s == 0) return nb;
+    const long long rest = (long long)n - (long long)s * segt * jt;
+    if (rest <= 0) return 0;
+    const long long rows = (rest + bi - 1) / bi - 1;
+    return rows > 0 ? (int)rows : 0;
+}
+
+// Symmetric j-tiles of row b.
+__host__ __device__ inline int row_tiles(int n, int bi, int jt, int b) {
+    const long long js = (long long)(b + 1) * bi;
+    return js < n ? (int)((n - js + jt - 1) / jt) : 0;
+}
+
+// Segments (i-planes) of row b.
+__host__ __device__ inline int row_segments(int n, int bi, int jt, int segt, int b) {
+    const int t = row_tiles(n, bi, jt, b);
+    return t > 0 ? (t + segt - 1) / segt : 1;
+}
+
+}  // namespace sym
 
 // Arguments of the pair kernel (FP32 structure-of-arrays input).
 struct PairArgs {
@@ -65,6 +102,21 @@ struct PairArgs {
     float eps2;   // fp32(eps^2)
     void *part;   // partial sums [nseg][words][npad]
     int npad;
+};
+
+// Arguments of the symmetric pair kernel (each unordered pair once; FP32
+// structure-of-arrays input).  Block rows of bi = 64 W IPL particles; row b's
+// symmetric range is split into segments of segt j-tiles.
+struct SymArgs {
+    const float *x, *y, *z, *m;
+    int n;
+    float eps2;
+    int segt;     // j-tiles per segment
+    int nb;       // block rows
+    int smax;     // segments of row 0 (the most of any row)
+    int npad;     // nb * bi
+    void *ipart;  // i-side partials [smax][words][npad]
+    void *jpart;  // j-side sums [nb - 1][4][npad]: FP64 (PLAIN: FP32)
 };
 
 // Arguments of the pair kernel on FP64 positions with per-i-tile reference centres.
@@ -247,15 +299,33 @@ inline bool misaligned(const T *p) {
     return reinterpret_cast<uintptr_t>(p) % alignof(T) != 0;
 }
 
+// Scratch of the symmetric engine: i-side partials [nseg][words][npad], then the
+// j-side sums [nb - 1][4][npad] (FP64; PLAIN: FP32).
+inline size_t sym_ipart_bytes(const TileCfg &c, int precision) {
+    const size_t b = (size_t)c.nseg * partial_words(precision) * (size_t)c.npad * 4;
+    return (b + 255) / 256 * 256;
+}
+inline size_t sym_jpart_bytes(const TileCfg &c, int precision) {
+    const size_t rows = c.nb > 1 ? (size_t)(c.nb - 1) : 0;
+    const size_t b = rows * kForceOutputs * (size_t)c.npad * (precision == NBODY_PLAIN ? 4 : 8);
+    return (b + 255) / 256 * 256;
+}
+
 // Host helpers (api.cpp).
 bool stream_capturing(hipStream_t s);
 nbody_status get_workspace(const nbody_opts &o, size_t need, hipStream_t s, void **out);
-// split_ok: the caller has a split-engine kernel for this evaluation.
+// engines (kEngine* bits of tuning.h): the engines besides the grid engine that the
+// caller has kernels for.
 nbody_status choose_cfg(int kernel, int64_t n, int precision, const nbody_opts &o, TileCfg *cfg,
-                        bool split_ok);
+                        int engines);
 // The same for ni i-particles against nj j-particles (nj >= 1).
 nbody_status choose_cfg_ij(int kernel, int64_t ni, int64_t nj, int precision, const nbody_opts &o,
-                           TileCfg *cfg, bool split_ok);
+                           TileCfg *cfg, int engines);
+// Engines of a single-set force evaluation with these options: split and symmetric,
+// except with per-i-tile centres (the grid engine's i-tiles).
+inline int force_engines(const nbody_opts &o) {
+    return o.centre != NBODY_CENTRE_TILE ? kEngineSplit | kEngineSym : 0;
+}
 size_t partial_bytes(const TileCfg &c, int precision, int outputs = kForceOutputs);
 size_t align_up(size_t v, size_t a);
 nbody_status check_common(int64_t n, const void *pos, const void *mass, float eps,
@@ -313,6 +383,9 @@ nbody_status launch_pair_split(const TileCfg &cfg, int precision, bool with_pot,
                                const PairArgs &a, const FinalizeArgs &f, hipStream_t s);
 nbody_status launch_vjp_split(const TileCfg &cfg, int precision, const VjpArgs &a, bool with_mass,
                               const VjpFinalizeArgs &f, hipStream_t s);
+// Symmetric engine (cfg.sym): pair kernel and its finalize (force_sym.hip).
+nbody_status launch_pair_sym(const TileCfg &cfg, int precision, bool with_pot,
+                             const PairArgs &a, const FinalizeArgs &f, hipStream_t s);
 nbody_status launch_pair_ij(const TileCfg &cfg, int precision, bool with_pot, const IJPairArgs &a,
                             hipStream_t s);
 // fp32(x - c) with c the FP64 mean of all positions (two kernels: block partial sums,

@@ -52,9 +52,15 @@ nbody_status nbody_force_noalloc(int64_t n, const float *pos, const float *mass,
     if (st) return st;
     if (o.workspace) return set_error(NBODY_EINVAL, "nbody_force_noalloc takes no workspace");
     TileCfg cfg;
-    if ((st = choose_cfg(KERNEL_FORCE, n, o.precision, o, &cfg, true))) return st;
+    if ((st = choose_cfg(KERNEL_FORCE, n, o.precision, o, &cfg, kEngineSplit | kEngineSym))) return st;
     size_t need = partial_bytes(cfg, o.precision);
-    if (need > kStaticScratchBytes && cfg.jl == 1 && o.nseg == 0 && cfg.nseg > 1) {
+    if (need > kStaticScratchBytes && cfg.sym && o.symmetric == 0) {
+        // The symmetric engine's j-side sums grow as n^2: the grid engine instead.
+        o.symmetric = 1;
+        if ((st = choose_cfg(KERNEL_FORCE, n, o.precision, o, &cfg, kEngineSplit))) return st;
+        need = partial_bytes(cfg, o.precision);
+    }
+    if (need > kStaticScratchBytes && cfg.jl == 1 && !cfg.sym && o.nseg == 0 && cfg.nseg > 1) {
         // Fewer j-segments (longer ones) until the partial sums fit.
         const size_t per_seg = need / cfg.nseg;  // at most 256 bytes of alignment over
         const int64_t fit = per_seg ? (int64_t)((kStaticScratchBytes - 256) / per_seg) : 0;
@@ -62,7 +68,7 @@ nbody_status nbody_force_noalloc(int64_t n, const float *pos, const float *mass,
             nbody_opts o2 = o;
             o2.nseg = (int32_t)fit;
             o2.jlanes = 1;
-            if ((st = choose_cfg(KERNEL_FORCE, n, o.precision, o2, &cfg, true))) return st;
+            if ((st = choose_cfg(KERNEL_FORCE, n, o.precision, o2, &cfg, kEngineSplit))) return st;
             need = partial_bytes(cfg, o.precision);
         }
     }

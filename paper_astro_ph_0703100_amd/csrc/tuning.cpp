@@ -3,11 +3,11 @@
 // File format (written by nbody_tune_save and by tune.py):
 //   {"version": 1, "arch": "gfx950", "entries": [
 //     {"kernel": 0, "precision": 2, "bucket": 17, "ipl": 4, "jtile": 256, "nseg": 16,
-//      "jlanes": 1}, ...]}
+//      "jlanes": 1, "symmetric": 0}, ...]}
 // kernel: 0 force, 1 adjoint, 2 batched, 3 force-jerk; precision: 0 plain, 1 FP64-reduced,
 // 2 compensated; bucket: floor(log2 n) of the particle count (batched: mean system
-// size); jlanes (1 if absent) selects the grid (1) or split (8..64) engine.  Unknown
-// keys are ignored.
+// size); jlanes (1 if absent) selects the grid (1) or split (8..64) engine, symmetric
+// (0 if absent) the symmetric engine.  Unknown keys are ignored.
 #include "tuning.h"
 
 #include <cctype>
@@ -27,7 +27,8 @@ std::mutex g_mu;
 bool g_set[KERNEL_COUNT][3][kBuckets];
 TuneEntry g_tab[KERNEL_COUNT][3][kBuckets];
 
-TuneEntry builtin(int kernel, int64_t n, bool split_ok) {
+TuneEntry builtin(int kernel, int64_t n, int engines) {
+    const bool split_ok = (engines & kEngineSplit) != 0;
     // Measured on MI355X (tune.py): one i-particle per lane (37 VGPRs, 8 waves per
     // SIMD) and many j-segments beat wider i-tiles for every kernel and size tried;
     // the j-split itself is chosen from n (nseg = 0).  Below 2^13 particles the force's
@@ -57,6 +58,11 @@ bool valid_entry(int kernel, int precision, int bucket, const TuneEntry &e) {
 }  // namespace
 
 bool valid_shape(int kernel, const TuneEntry &e) {
+    if (e.sym)
+        // Symmetric engine: single-set force, 512 ipl particles per block row.
+        return kernel == KERNEL_FORCE && e.sym == 1 && e.jl == 1 &&
+               (e.ipl == 1 || e.ipl == 2 || e.ipl == 4) && (e.jt == 64 || e.jt == 128) &&
+               e.nseg >= 0 && e.nseg <= kMaxSeg;
     if (e.jl == 1)
         return (e.ipl == 1 || e.ipl == 2 || e.ipl == 4 || e.ipl == 8) &&
                (e.jt == 64 || e.jt == 128 || e.jt == 256 || e.jt == 512) && e.nseg >= 0 &&
@@ -77,14 +83,18 @@ int size_bucket(int64_t n) {
     return b;
 }
 
-TuneEntry tuned_shape(int kernel, int precision, int64_t n, bool split_ok) {
+TuneEntry tuned_shape(int kernel, int precision, int64_t n, int engines) {
     if (kernel < 0 || kernel >= KERNEL_COUNT || precision < 0 || precision > 2)
-        return builtin(0, n, false);
+        return builtin(0, n, 0);
     std::lock_guard<std::mutex> lk(g_mu);
     const int b = size_bucket(n);
-    if (g_set[kernel][precision][b] && (split_ok || g_tab[kernel][precision][b].jl == 1))
-        return g_tab[kernel][precision][b];
-    return builtin(kernel, n, split_ok);
+    if (g_set[kernel][precision][b]) {
+        const TuneEntry &e = g_tab[kernel][precision][b];
+        const bool usable = e.sym ? (engines & kEngineSym) != 0
+                                  : (e.jl == 1 || (engines & kEngineSplit) != 0);
+        if (usable) return e;
+    }
+    return builtin(kernel, n, engines);
 }
 
 void set_tuned_shape(int kernel, int precision, int64_t n, const TuneEntry &e) {
@@ -102,9 +112,9 @@ using namespace nbody;
 extern "C" {
 
 nbody_status nbody_tune_set(int32_t kernel, int32_t precision, int64_t n, int32_t ipl,
-                            int32_t jtile, int32_t nseg, int32_t jlanes) {
+                            int32_t jtile, int32_t nseg, int32_t jlanes, int32_t symmetric) {
     clear_error();
-    const TuneEntry e{ipl, jtile, nseg, jlanes};
+    const TuneEntry e{ipl, jtile, nseg, jlanes, symmetric};
     if (n < 1 || !valid_entry(kernel, precision, size_bucket(n), e))
         return set_error(NBODY_EINVAL, "invalid tuning entry");
     set_tuned_shape(kernel, precision, n, e);
@@ -115,11 +125,12 @@ nbody_status nbody_tune_get(int32_t kernel, int32_t precision, int64_t n, int32_
     clear_error();
     if (!shape || kernel < 0 || kernel >= KERNEL_COUNT || precision < 0 || precision > 2 || n < 1)
         return set_error(NBODY_EINVAL, "invalid tuning query");
-    const TuneEntry e = tuned_shape(kernel, precision, n, true);
+    const TuneEntry e = tuned_shape(kernel, precision, n, kEngineSplit | kEngineSym);
     shape[0] = e.ipl;
     shape[1] = e.jt;
     shape[2] = e.nseg;
     shape[3] = e.jl;
+    shape[4] = e.sym;
     return NBODY_OK;
 }
 
@@ -145,8 +156,9 @@ nbody_status nbody_tune_save(const char *path) {
                     if (g_set[k][p][b]) {
                         const TuneEntry &e = g_tab[k][p][b];
                         std::fprintf(f, "%s\n  {\"kernel\": %d, \"precision\": %d, \"bucket\": %d, "
-                                        "\"ipl\": %d, \"jtile\": %d, \"nseg\": %d, \"jlanes\": %d}",
-                                     first ? "" : ",", k, p, b, e.ipl, e.jt, e.nseg, e.jl);
+                                        "\"ipl\": %d, \"jtile\": %d, \"nseg\": %d, \"jlanes\": %d, "
+                                        "\"symmetric\": %d}",
+                                     first ? "" : ",", k, p, b, e.ipl, e.jt, e.nseg, e.jl, e.sym);
                         first = false;
                     }
     }
@@ -183,17 +195,17 @@ nbody_status nbody_tune_load(const char *path) {
         if (ob == std::string::npos || ob > end) break;
         const size_t cb = text.find('}', ob);
         if (cb == std::string::npos) return set_error(NBODY_EINVAL, "malformed tuning entry");
-        int v[7] = {-1, -1, -1, -1, -1, -1, 1};  // jlanes absent: grid engine
-        const char *keys[7] = {"\"kernel\"", "\"precision\"", "\"bucket\"", "\"ipl\"",
-                               "\"jtile\"",  "\"nseg\"",      "\"jlanes\""};
-        for (int q = 0; q < 7; ++q) {
+        int v[8] = {-1, -1, -1, -1, -1, -1, 1, 0};  // jlanes, symmetric absent: grid engine
+        const char *keys[8] = {"\"kernel\"", "\"precision\"", "\"bucket\"", "\"ipl\"",
+                               "\"jtile\"",  "\"nseg\"",      "\"jlanes\"", "\"symmetric\""};
+        for (int q = 0; q < 8; ++q) {
             const size_t kp = text.find(keys[q], ob);
             if (kp == std::string::npos || kp > cb) continue;
             const size_t colon = text.find(':', kp);
             if (colon == std::string::npos || colon > cb) continue;
             v[q] = std::atoi(text.c_str() + colon + 1);
         }
-        const TuneEntry e{v[3], v[4], v[5], v[6]};
+        const TuneEntry e{v[3], v[4], v[5], v[6], v[7]};
         if (!valid_entry(v[0], v[1], v[2], e))
             return set_error(NBODY_EINVAL, "invalid tuning entry in " + std::string(path));
         entries.push_back({v[0], v[1], v[2], e});

@@ -42,9 +42,11 @@ def test_opts_layout_and_defaults():
     assert o.precision == _lib.NBODY_COMP
     assert o.centre == _lib.NBODY_CENTRE_SYSTEM
     assert o.self_pot == 0 and o.ipl == 0 and o.jtile == 0 and o.nseg == 0 and o.jlanes == 0
+    assert o.symmetric == 0
     assert not o.workspace and o.workspace_bytes == 0
-    # seven int32 fields, padding to 8, a pointer and a size_t (the header's layout)
+    # eight int32 fields, a pointer and a size_t (the header's layout)
     assert ctypes.sizeof(_lib.nbody_opts) == 48
+    assert _lib.nbody_opts.symmetric.offset == 28
     assert _lib.nbody_opts.workspace.offset == 32
     assert _lib.nbody_version().startswith("nbody")
 
@@ -160,6 +162,7 @@ def test_force_ij_empty_i_set_is_a_no_op():
     ("precision", 3), ("precision", -1), ("self_pot", 2), ("centre", 5),
     ("ipl", 3), ("jtile", 100), ("nseg", -2), ("nseg", 100000),
     ("jlanes", -1), ("jlanes", 3), ("jlanes", 4), ("jlanes", 128),
+    ("symmetric", -1), ("symmetric", 3),
 ])
 def test_force_ex_rejects_bad_options(field, value):
     o = _lib.nbody_opts_default()
@@ -175,6 +178,57 @@ def test_force_ex_rejects_bad_split_shapes(ipl, jtile, nseg, jlanes):
     o.ipl, o.jtile, o.nseg, o.jlanes = ipl, jtile, nseg, jlanes
     st = _lib.nbody_force_ex(4096, FAKE, FAKE, 0.1, FAKE, FAKE, o, None, check=False)
     assert st == _lib.NBODY_EINVAL, _lib.nbody_last_error()
+
+
+@pytest.mark.parametrize("ipl,jtile,nseg,jlanes", [
+    (8, 128, 0, 0), (3, 64, 0, 0), (1, 256, 0, 0), (1, 32, 0, 0), (1, 128, 0, 16),
+    (2, 128, 5000, 0)])
+def test_force_ex_rejects_bad_symmetric_shapes(ipl, jtile, nseg, jlanes):
+    o = _lib.nbody_opts_default()
+    o.ipl, o.jtile, o.nseg, o.jlanes, o.symmetric = ipl, jtile, nseg, jlanes, 2
+    st = _lib.nbody_force_ex(4096, FAKE, FAKE, 0.1, FAKE, FAKE, o, None, check=False)
+    assert st == _lib.NBODY_EINVAL, _lib.nbody_last_error()
+
+
+def test_symmetric_engine_refused_where_not_built():
+    """symmetric = 2 where there is no symmetric kernel (separate sets, force-jerk, the
+    adjoint, tile centres, batched plans): NBODY_EUNSUPPORTED before anything is
+    enqueued."""
+    o = _lib.nbody_opts_default()
+    o.symmetric = 2
+    assert _lib.nbody_force_ij(10, FAKE, None, 10, FAKE, FAKE, 0.1, FAKE, None, o, None,
+                               check=False) == _lib.NBODY_EUNSUPPORTED
+    assert _lib.nbody_force_jerk(10, FAKE, FAKE, FAKE, 0.1, FAKE, FAKE, None, o, None,
+                                 check=False) == _lib.NBODY_EUNSUPPORTED
+    assert _lib.nbody_force_vjp(10, FAKE, FAKE, 0.1, FAKE, None, FAKE, None, o, None,
+                                check=False) == _lib.NBODY_EUNSUPPORTED
+    o.centre = _lib.NBODY_CENTRE_TILE
+    assert _lib.nbody_force_f64(10, FAKE, FAKE, 0.1, FAKE, None, o, None,
+                                check=False) == _lib.NBODY_EUNSUPPORTED
+    o.centre = _lib.NBODY_CENTRE_SYSTEM
+    arr = (ctypes.c_int64 * 3)(0, 5, 9)
+    h = ctypes.c_void_p()
+    assert _lib.load().nbody_plan_create_batched(2, arr, ctypes.byref(o), ctypes.byref(h)) == \
+        _lib.NBODY_EUNSUPPORTED
+    assert h.value is None
+
+
+def test_symmetric_workspace_size():
+    """The symmetric engine's scratch: i-side partials per work-item segment plus the
+    j-side sums of every block row but the last, FP64 (PLAIN: FP32)."""
+    o = _lib.nbody_opts_default()
+    o.symmetric, o.ipl, o.jtile, o.nseg = 2, 1, 128, 4
+    n = 5000  # block rows of 512: 10 rows, npad 5120; row 0 has 36 tiles -> 9 per item
+    rows, npad, segs = 9, 5120, 4
+    # (the FP64-position path adds FP32 positions and the centre partials)
+    extra = 3 * 4 * n + 8192 + 768
+    want = segs * 8 * npad * 4 + rows * 4 * npad * 8
+    got = _lib.nbody_workspace_size(n, o)
+    assert want <= got <= want + extra
+    o.precision = _lib.NBODY_PLAIN
+    want = segs * 4 * npad * 4 + rows * 4 * npad * 4
+    got = _lib.nbody_workspace_size(n, o)
+    assert want <= got <= want + extra
 
 
 def test_split_engine_refused_where_not_built():
@@ -356,9 +410,9 @@ def test_tuning_table_roundtrip(tmp_path):
     _lib.nbody_tune_set(_lib.NBODY_KERNEL_FORCE, _lib.NBODY_COMP, 131072, 8, 512, 12)
     _lib.nbody_tune_set(_lib.NBODY_KERNEL_VJP, _lib.NBODY_PLAIN, 5000, 1, 64, 3)
     _lib.nbody_tune_set(_lib.NBODY_KERNEL_FORCE, _lib.NBODY_FP64RED, 3000, 2, 1024, 0, 32)
-    assert _lib.nbody_tune_get(_lib.NBODY_KERNEL_FORCE, _lib.NBODY_COMP, 131072) == (8, 512, 12, 1)
+    assert _lib.nbody_tune_get(_lib.NBODY_KERNEL_FORCE, _lib.NBODY_COMP, 131072) == (8, 512, 12, 1, 0)
     # Same size bucket (floor(log2 n) = 17), other precision untouched.
-    assert _lib.nbody_tune_get(_lib.NBODY_KERNEL_FORCE, _lib.NBODY_COMP, 200000) == (8, 512, 12, 1)
+    assert _lib.nbody_tune_get(_lib.NBODY_KERNEL_FORCE, _lib.NBODY_COMP, 200000) == (8, 512, 12, 1, 0)
     assert _lib.nbody_tune_get(_lib.NBODY_KERNEL_FORCE, _lib.NBODY_PLAIN, 131072) == base
     path = tmp_path / "t.json"
     _lib.nbody_tune_save(path)
@@ -366,15 +420,15 @@ def test_tuning_table_roundtrip(tmp_path):
     _lib.nbody_tune_reset()
     assert _lib.nbody_tune_get(_lib.NBODY_KERNEL_FORCE, _lib.NBODY_COMP, 131072) == base
     _lib.nbody_tune_load(path)
-    assert _lib.nbody_tune_get(_lib.NBODY_KERNEL_FORCE, _lib.NBODY_COMP, 131072) == (8, 512, 12, 1)
-    assert _lib.nbody_tune_get(_lib.NBODY_KERNEL_VJP, _lib.NBODY_PLAIN, 4096) == (1, 64, 3, 1)
-    assert _lib.nbody_tune_get(_lib.NBODY_KERNEL_FORCE, _lib.NBODY_FP64RED, 2048) == (2, 1024, 0, 32)
+    assert _lib.nbody_tune_get(_lib.NBODY_KERNEL_FORCE, _lib.NBODY_COMP, 131072) == (8, 512, 12, 1, 0)
+    assert _lib.nbody_tune_get(_lib.NBODY_KERNEL_VJP, _lib.NBODY_PLAIN, 4096) == (1, 64, 3, 1, 0)
+    assert _lib.nbody_tune_get(_lib.NBODY_KERNEL_FORCE, _lib.NBODY_FP64RED, 2048) == (2, 1024, 0, 32, 0)
     # A file without "jlanes" keys (the earlier format) loads as grid-engine shapes.
     old = tmp_path / "old.json"
     old.write_text('{"entries": [{"kernel": 0, "precision": 2, "bucket": 12, "ipl": 2, '
                    '"jtile": 128, "nseg": 5}]}')
     _lib.nbody_tune_load(old)
-    assert _lib.nbody_tune_get(_lib.NBODY_KERNEL_FORCE, _lib.NBODY_COMP, 4096) == (2, 128, 5, 1)
+    assert _lib.nbody_tune_get(_lib.NBODY_KERNEL_FORCE, _lib.NBODY_COMP, 4096) == (2, 128, 5, 1, 0)
     _lib.nbody_tune_reset()
     # Workspace sizing follows the table.
     o = _lib.nbody_opts_default()
@@ -394,7 +448,11 @@ def test_tuning_table_roundtrip(tmp_path):
 
 
 def test_tuning_rejects_bad_entries(tmp_path):
-    bad = _lib.load().nbody_tune_set
+    raw = _lib.load().nbody_tune_set
+
+    def bad(k, p, n, ipl, jt, nseg, jl, sym=0):
+        return raw(k, p, n, ipl, jt, nseg, jl, sym)
+
     assert bad(0, 2, 1000, 3, 256, 0, 1) == _lib.NBODY_EINVAL
     assert bad(0, 2, 1000, 4, 100, 0, 1) == _lib.NBODY_EINVAL
     assert bad(5, 2, 1000, 4, 256, 0, 1) == _lib.NBODY_EINVAL
@@ -409,6 +467,15 @@ def test_tuning_rejects_bad_entries(tmp_path):
     assert bad(2, 2, 1000, 1, 512, 0, 16) == _lib.NBODY_EINVAL
     assert bad(3, 2, 1000, 1, 512, 0, 16) == _lib.NBODY_EINVAL
     assert bad(0, 2, 1000, 1, 512, 0, 0) == _lib.NBODY_EINVAL
+    # symmetric-engine entries: force only, jlanes 1, ipl 1, 2 or 4, jtile 64 or 128
+    assert bad(0, 2, 1000, 4, 128, 0, 1, 1) == _lib.NBODY_OK
+    assert bad(1, 2, 1000, 1, 128, 0, 1, 1) == _lib.NBODY_EINVAL
+    assert bad(3, 2, 1000, 1, 128, 0, 1, 1) == _lib.NBODY_EINVAL
+    assert bad(0, 2, 1000, 8, 128, 0, 1, 1) == _lib.NBODY_EINVAL
+    assert bad(0, 2, 1000, 1, 256, 0, 1, 1) == _lib.NBODY_EINVAL
+    assert bad(0, 2, 1000, 1, 128, 0, 16, 1) == _lib.NBODY_EINVAL
+    assert bad(0, 2, 1000, 1, 128, 0, 1, 2) == _lib.NBODY_EINVAL
+    _lib.nbody_tune_reset()
     bad = tmp_path / "bad.json"
     bad.write_text('{"entries": [{"kernel": 0, "precision": 2, "bucket": 17, "ipl": 3, '
                    '"jtile": 256, "nseg": 0}]}')

@@ -32,7 +32,7 @@ def test_roofline_fields():
     im = r["issue_model"]
     assert im["peak_pairs_per_s"] == pytest.approx(256 * 4 * 32 * 2.4e9 / 17)
     assert im["frac"] == pytest.approx(pairs / 5e-3 / im["peak_pairs_per_s"])
-    for kind, slots in (("jerk", 31), ("adjoint", 42)):
+    for kind, slots in (("jerk", 31), ("adjoint", 35)):
         assert bench.peak_pairs(kind) == pytest.approx(256 * 4 * 32 * 2.4e9 / slots)
     f = bench.fractions("adjoint", pairs, 5.0)
     assert f["frac"] == pytest.approx(pairs * 45 / 5e-3 / 157.3e12)

@@ -113,7 +113,7 @@ def test_plummer_2048_default_shape():
     p, m, x64, m64 = to_dev(pos, mass)
     eps = float(np.float32(w.eps))
     ra, rp = oracle.force_all(x64, m64, eps)
-    ipl, jt, _, jl = _lib.nbody_tune_get(_lib.NBODY_KERNEL_FORCE, _lib.NBODY_COMP, w.n)
+    ipl, jt, _, jl, _ = _lib.nbody_tune_get(_lib.NBODY_KERNEL_FORCE, _lib.NBODY_COMP, w.n)
     for precision in ("comp", "fp64red", "plain"):
         acc, pot = api.force(p, m, eps, precision=precision)
         torch.cuda.synchronize()

@@ -40,7 +40,7 @@ def test_force_sweep_admits_every_shape_and_the_table_serves_the_best():
     _lib.nbody_tune_set(_lib.KERNELS["force"], _lib.PRECISIONS["comp"], n, best["ipl"],
                         best["jtile"], best["nseg"], best["jlanes"])
     assert _lib.nbody_tune_get(_lib.KERNELS["force"], _lib.PRECISIONS["comp"], n) == \
-        (best["ipl"], best["jtile"], best["nseg"], best["jlanes"])
+        (best["ipl"], best["jtile"], best["nseg"], best["jlanes"], 0)
     pos, _, mass = ics.plummer(n, seed=7)
     p = torch.from_numpy(np.ascontiguousarray(pos.T.astype(np.float32))).to(DEV)
     m = torch.from_numpy(mass.astype(np.float32)).to(DEV)
