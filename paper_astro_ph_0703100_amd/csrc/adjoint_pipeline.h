@@ -15,7 +15,12 @@
 // [0..2] sum_j (m_k g_j / s^3 - e d) with e = (q + 3 (d . w) / s^2) / s^3, [3] B_k,
 // [4] the positive sum of dL/dm_k.  The engine hands the j == k pair a record with no
 // mass and no cotangents (null_j), which adds exactly zero to every sum.
-// 31 VALU operations and one v_rsq_f32 per pair (38 when w was formed per pair).
+// 31 VALU operations and one v_rsq_f32 per pair (38 when w was formed per pair).  The
+// terms of -(d . w), -q and -e are formed instead of those of d . w, q and e (the i-record
+// carries -m_k and -p_k): rounding to nearest is symmetric in sign, so every value is
+// the exact negation and the sums are bitwise the same, but each step is an FMA that
+// accumulates into its own addend (VOP2, issued in half the time of a VOP3 FMA or of a
+// multiplication with a negated operand).
 #pragma once
 
 #include "tile_engine.h"
@@ -31,15 +36,23 @@ struct Adjoint {
     static constexpr int kBlockJ = nbody::kBlockJ;
     using Args = VjpArgs;
     struct IState {
-        float x, y, z, m, gx, gy, gz, p;
+        float x, y, z, m, nm, gx, gy, gz, np;  // nm = -m_k, np = -p_k
     };
     struct Ctx {};
     static __device__ __forceinline__ int n_i(const Args &a) { return a.n; }
     static __device__ __forceinline__ int n_j(const Args &a) { return a.n; }
     static __device__ __forceinline__ Ctx make_ctx(const Args &, int) { return {}; }
     static __device__ __forceinline__ IState load_i(const Args &a, const Ctx &, int i) {
-        return {a.x[i], a.y[i], a.z[i], a.m[i], (float)a.gx[i], (float)a.gy[i], (float)a.gz[i],
-                a.gp ? (float)a.gp[i] : 0.0f};
+        const float m = a.m[i];
+        return {a.x[i], a.y[i], a.z[i], m, negated(m), (float)a.gx[i], (float)a.gy[i],
+                (float)a.gz[i], a.gp ? -(float)a.gp[i] : -0.0f};
+    }
+    // -m held in a register of its own: left visible as the negation of m, the compiler
+    // would fold it into the FMAs as a source modifier, which takes the 64-bit encoding.
+    static __device__ __forceinline__ float negated(float m) {
+        float r = -m;
+        asm volatile("" : "+v"(r));
+        return r;
     }
     static __device__ __forceinline__ void load_j(const Args &a, const Ctx &, int j, float (&r)[8]) {
         r[0] = a.x[j];
@@ -83,17 +96,17 @@ struct Adjoint {
         gkd = __builtin_fmaf(k.gy, dy, gkd);
         gkd = __builtin_fmaf(k.gz, dz, gkd);
         const float mgkd = j[3] * gkd;
-        const float dw = __builtin_fmaf(k.m, gd, -mgkd);  // d . w
-        const float mp = j[3] * k.p;
-        const float q = __builtin_fmaf(k.m, j[7], mp);
+        const float ndw = __builtin_fmaf(k.nm, gd, mgkd);  // -(d . w)
+        const float nmp = j[3] * k.np;
+        const float nq = __builtin_fmaf(k.nm, j[7], nmp);  // -q
         const float t3 = r2 * 3.0f;
-        const float e = r3 * __builtin_fmaf(t3, dw, q);
+        const float ne = r3 * __builtin_fmaf(t3, ndw, nq);  // -e
         acc[0] = __builtin_fmaf(kr3, j[4], acc[0]);
         acc[1] = __builtin_fmaf(kr3, j[5], acc[1]);
         acc[2] = __builtin_fmaf(kr3, j[6], acc[2]);
-        acc[0] = __builtin_fmaf(-e, dx, acc[0]);
-        acc[1] = __builtin_fmaf(-e, dy, acc[1]);
-        acc[2] = __builtin_fmaf(-e, dz, acc[2]);
+        acc[0] = __builtin_fmaf(ne, dx, acc[0]);
+        acc[1] = __builtin_fmaf(ne, dy, acc[1]);
+        acc[2] = __builtin_fmaf(ne, dz, acc[2]);
         acc[3] = __builtin_fmaf(j[3], r3, acc[3]);
         if (MASS) {
             acc[4] = __builtin_fmaf(gd, r3, acc[4]);
@@ -121,8 +134,10 @@ struct AdjointTile {
         return {c[0], c[1], c[2]};
     }
     static __device__ __forceinline__ IState load_i(const Args &a, const Ctx &c, int i) {
-        return {(float)(a.x[i] - c.cx), (float)(a.y[i] - c.cy), (float)(a.z[i] - c.cz), a.m[i],
-                (float)a.gx[i], (float)a.gy[i], (float)a.gz[i], a.gp ? (float)a.gp[i] : 0.0f};
+        const float m = a.m[i];
+        return {(float)(a.x[i] - c.cx), (float)(a.y[i] - c.cy), (float)(a.z[i] - c.cz), m,
+                Adjoint::negated(m), (float)a.gx[i], (float)a.gy[i], (float)a.gz[i],
+                a.gp ? -(float)a.gp[i] : -0.0f};
     }
     static __device__ __forceinline__ void load_j(const Args &a, const Ctx &c, int j, float (&r)[8]) {
         r[0] = (float)(a.x[j] - c.cx);
