@@ -164,7 +164,7 @@ nbody_status choose_cfg_ij(int kernel, int64_t ni, int64_t nj, int precision, co
             for (int b = 0; b < c.nb; ++b) all += sym::row_tiles(n, bi, c.jt, b);
             segt = all / ((int64_t)device_info().cus * 16);
         }
-        c.segt = (int)std::max<int64_t>(1, segt);
+        c.segt = (int)std::max<int64_t>(1, std::min<int64_t>(segt, t0));  // at most a whole row
         c.nseg = sym::row_segments(n, bi, c.jt, c.segt, 0);
         int64_t items = 0;
         for (int s = 0; s < c.nseg; ++s) items += sym::items_of_segment(n, bi, c.jt, c.segt, c.nb, s);

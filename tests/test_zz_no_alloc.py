@@ -40,7 +40,8 @@ def ex(n, p, m, eps, opts):
 
 @pytest.mark.parametrize("shape", [dict(ipl=1, jtile=256, nseg=40, jlanes=1),
                                    dict(ipl=2, jtile=128, nseg=7, jlanes=1),
-                                   dict(ipl=1, jtile=512, jlanes=64)])
+                                   dict(ipl=1, jtile=512, jlanes=64),
+                                   dict(ipl=4, jtile=64, nseg=8, symmetric=2)])
 def test_noalloc_matches_force_ex_bitwise_on_two_calls(shape):
     eps = 0.01
     for n, seed in ((40000, 1), (5003, 2)):  # second call smaller
@@ -72,3 +73,24 @@ def test_noalloc_default_shape_at_the_paper_size_then_smaller():
         ra, rp = oracle.force_sampled(p32.T.astype(np.float64), m32.astype(np.float64), eps, idx)
         assert rel_errors(a1[idx], ra)["rel_rms"] <= 1e-6
         assert rel_errors(q1[idx], rp)["rel_rms"] <= 1e-6
+
+
+def test_noalloc_symmetric_table_entry_falls_back_to_the_grid_engine():
+    """A tuned symmetric-engine shape whose j-side sums do not fit the static array
+    (N = 131072) is replaced by the grid engine's; an explicit symmetric = 2 is refused."""
+    w = ics.WORKLOADS["plummer_131072"]
+    eps = float(np.float32(w.eps))
+    p, m, _, _ = inputs(w.n, w.seed)
+    try:
+        _lib.nbody_tune_set(_lib.NBODY_KERNEL_FORCE, _lib.NBODY_COMP, w.n, 4, 64, 0, 1, 1)
+        a1, q1 = noalloc(w.n, p, m, eps, api.make_opts())
+        a2, q2 = ex(w.n, p, m, eps, api.make_opts(symmetric=1))
+        torch.cuda.synchronize()
+        assert rel_errors(a1.cpu().numpy().T, a2.cpu().numpy().T)["rel_rms"] <= 1e-6
+        assert rel_errors(q1.cpu().numpy(), q2.cpu().numpy())["rel_rms"] <= 1e-6
+        with pytest.raises(_lib.NBodyError) as e:
+            noalloc(w.n, p, m, eps, api.make_opts(symmetric=2))
+        assert e.value.status == _lib.NBODY_EINVAL and "static scratch" in str(e.value)
+    finally:
+        _lib.nbody_tune_reset()
+        _lib.nbody_tune_load(_lib.TUNING_PATH)
