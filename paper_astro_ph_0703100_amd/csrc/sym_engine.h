@@ -35,12 +35,12 @@
 // No atomics: every result is a fixed-order sum, bitwise reproducible per launch
 // shape (W, IPL, JT, segt).
 //
-// Issue cost per unordered pair with the potential (gfx950 issues a 32-bit-encoded
-// VALU operation of a wavefront in 2 cycles, a 64-bit-encoded one, VOP3 or DPP, in 4,
-// v_rsq_f32 in 8): 3 separations, s^2 (one VOP3 FMA, two FMACs), rsq, r^2, and per side
-// m r, m r^3, three FMACs and one addition: 48 cycles, against 2 x 36 for the two
-// ordered pairs; the rotation of the j-sums adds 14 cycles per step, shared by the
-// lane's IPL pairs of that step.
+// Issue cost per unordered pair with the potential, in clocks per wavefront as measured
+// on gfx950 (two-operand operations 2, FMACs about 2.6, an FMA with a scalar addend and
+// any DPP-modified operation 4, v_rsq_f32 8): 3 separations, s^2 (one scalar-addend FMA,
+// two FMACs), rsq, r^2, and per side m r, m r^3, three FMACs and one addition: about 53,
+// against 2 x 39 for the two ordered pairs of the tile engine; the rotation of the
+// j-sums adds about 12 per step, shared by the lane's IPL pairs of that step.
 #pragma once
 
 #include <utility>
