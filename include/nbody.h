@@ -111,10 +111,11 @@ typedef struct nbody_opts {
  *     sums are accumulated as in the grid engine, the j-side sums per wavefront (FP32,
  *     64 * ipl terms) and over the block's 8 wavefronts in FP64 (PLAIN: FP32), and a
  *     second kernel adds both per particle in a fixed order.  Scratch grows as
- *     n^2 / (512 * ipl) words.  Available for nbody_force, nbody_force_ex,
- *     nbody_force_f64 and the leapfrog, not with NBODY_CENTRE_TILE.  On MI355X it
- *     runs about as fast as the grid engine (the lane-to-lane moves of the j-side sums
- *     cost what the halved pair work saves), so it is never chosen by default.
+ *     n^2 / (256 * ipl) FP64 values (PLAIN: FP32).  Available for nbody_force,
+ *     nbody_force_ex, nbody_force_f64 and the leapfrog, not with NBODY_CENTRE_TILE.  On
+ *     MI355X it runs about as fast as the grid engine (the lane-to-lane moves of the
+ *     j-side sums cost what the halved pair work saves), so it is never chosen by
+ *     default.
  * jlanes = 0 and symmetric = 0 with ipl, jtile and nseg all 0 take the shape from the
  * tuning table (any engine); with any of them set the grid engine is used unless
  * jlanes > 1 or symmetric = 2 selects another.  Results are bitwise reproducible for

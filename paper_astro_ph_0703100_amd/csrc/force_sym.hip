@@ -9,8 +9,8 @@ namespace {
 
 // Finalize arguments of the symmetric engine beyond the tile engine's.
 struct SymFinal {
-    const void *jpart;  // [nb - 1][4][npad], FP64 (PLAIN: FP32)
-    int bi, jt, segt;
+    const void *jpart;  // rows 0 .. nb - 2 (sym::jrow_base), FP64 (PLAIN: FP32)
+    int bi, jt, segt, nb;
 };
 
 // Fixed order per particle i of block row q: its row's segment partials (as the tile
@@ -27,18 +27,22 @@ __global__ __launch_bounds__(256) void sym_finalize_kernel(FinalizeArgs a, SymFi
         const double si = engine::sum_partial_output<kForceOutputs, MODE, BATCH>(
             a.part, nseg, (size_t)a.npad, i, o);
         using T = typename std::conditional<MODE == NBODY_PLAIN, float, double>::type;
-        const T *p = static_cast<const T *>(f.jpart) + (size_t)o * a.npad + i;
-        const size_t step = (size_t)kForceOutputs * a.npad;
+        const T *p = static_cast<const T *>(f.jpart);
+        // Particle i's output o in row b's j-plane.
+        auto at = [&](int b) {
+            return p[sym::jrow_base(f.nb, f.bi, b) + (size_t)o * sym::jrow_len(f.nb, f.bi, b) +
+                     (size_t)(i - (b + 1) * f.bi)];
+        };
         T r = (T)si;
         int b = 0;
         for (; b + BATCH <= q; b += BATCH) {
             T v[BATCH];
 #pragma unroll
-            for (int k = 0; k < BATCH; ++k) v[k] = p[(size_t)(b + k) * step];
+            for (int k = 0; k < BATCH; ++k) v[k] = at(b + k);
 #pragma unroll
             for (int k = 0; k < BATCH; ++k) r = r + v[k];
         }
-        for (; b < q; ++b) r = r + p[(size_t)b * step];
+        for (; b < q; ++b) r = r + at(b);
         return (double)r;
     });
 }
@@ -97,7 +101,7 @@ nbody_status launch_pair_sym(const TileCfg &cfg, int precision, bool with_pot,
                a.part, static_cast<char *>(a.part) + ibytes};
     hipLaunchKernelGGL(fn, dim3(cfg.nitems), dim3(64 * kSymWaves), 0, s, sa);
     NBODY_HIP_CHECK(hipGetLastError());
-    const SymFinal sf{sa.jpart, bi, cfg.jt, cfg.segt};
+    const SymFinal sf{sa.jpart, bi, cfg.jt, cfg.segt, cfg.nb};
     const int outputs = f.pot ? 4 : 3;
     const dim3 grid((f.n + 255) / 256, outputs);
     switch (precision) {

@@ -92,6 +92,17 @@ __host__ __device__ inline int row_segments(int n, int bi, int jt, int segt, int
     return t > 0 ? (t + segt - 1) / segt : 1;
 }
 
+// j-side sums of block row b cover j in [(b + 1) bi, nb bi): rows of decreasing length
+// stored back to back as [b][output][j - (b + 1) bi].  Length of row b (per output) and
+// its first element.
+__host__ __device__ inline size_t jrow_len(int nb, int bi, int b) {
+    return (size_t)(nb - 1 - b) * bi;
+}
+__host__ __device__ inline size_t jrow_base(int nb, int bi, int b) {
+    // kForceOutputs x sum over b' < b of (nb - 1 - b') bi
+    return (size_t)kForceOutputs * bi * ((size_t)b * (nb - 1) - (size_t)b * (b - 1) / 2);
+}
+
 }  // namespace sym
 
 // Arguments of the pair kernel (FP32 structure-of-arrays input).
@@ -116,7 +127,7 @@ struct SymArgs {
     int smax;     // segments of row 0 (the most of any row)
     int npad;     // nb * bi
     void *ipart;  // i-side partials [smax][words][npad]
-    void *jpart;  // j-side sums [nb - 1][4][npad]: FP64 (PLAIN: FP32)
+    void *jpart;  // j-side sums, rows of sym::jrow_len words per output: FP64 (PLAIN: FP32)
 };
 
 // Arguments of the pair kernel on FP64 positions with per-i-tile reference centres.
@@ -300,14 +311,15 @@ inline bool misaligned(const T *p) {
 }
 
 // Scratch of the symmetric engine: i-side partials [nseg][words][npad], then the
-// j-side sums [nb - 1][4][npad] (FP64; PLAIN: FP32).
+// j-side sums of rows 0 .. nb - 2 (sym::jrow_base; FP64, PLAIN: FP32).
 inline size_t sym_ipart_bytes(const TileCfg &c, int precision) {
     const size_t b = (size_t)c.nseg * partial_words(precision) * (size_t)c.npad * 4;
     return (b + 255) / 256 * 256;
 }
 inline size_t sym_jpart_bytes(const TileCfg &c, int precision) {
-    const size_t rows = c.nb > 1 ? (size_t)(c.nb - 1) : 0;
-    const size_t b = rows * kForceOutputs * (size_t)c.npad * (precision == NBODY_PLAIN ? 4 : 8);
+    if (c.nb < 2) return 0;
+    const size_t words = sym::jrow_base(c.nb, kSymWaves * 64 * c.ipl, c.nb - 1);
+    const size_t b = words * (precision == NBODY_PLAIN ? 4 : 8);
     return (b + 255) / 256 * 256;
 }
 

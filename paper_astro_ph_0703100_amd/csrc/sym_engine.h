@@ -29,7 +29,7 @@
 //     throughout (PLAIN); written at the end of the item to the i-plane of segment s;
 //   * j-side sums: FP32 per wave (its 64 IPL terms per record), then, after the tile's
 //     barrier, the W slices are added in a fixed order in FP64 (PLAIN: FP32) and
-//     written to the j-plane of row b;
+//     written to the j-plane of row b (which covers only j >= (b + 1) BI);
 //   * the finalize adds, for a particle of row q, the segment partials of its row and
 //     then the j-planes of rows 0 .. q - 1, in that fixed order.
 // No atomics: every result is a fixed-order sum, bitwise reproducible per launch
@@ -298,7 +298,8 @@ __global__ __launch_bounds__(64 * W) void sym_kernel(SymArgs a) {
             // Fixed-order sum of the W wave slices of this tile, one (record, output)
             // per thread, into row b's j-plane.
             const int jt0 = tile_base(t);
-            JT_t *jp = static_cast<JT_t *>(a.jpart) + (size_t)b * NO * a.npad;
+            JT_t *jp = static_cast<JT_t *>(a.jpart) + jrow_base(a.nb, BI, b);
+            const size_t len = jrow_len(a.nb, BI, b);
 #pragma unroll
             for (int q = tid; q < NO * JT; q += NT) {
                 const int o = q / JT;
@@ -309,7 +310,7 @@ __global__ __launch_bounds__(64 * W) void sym_kernel(SymArgs a) {
 #pragma unroll
                     for (int w = 1; w < W; ++w)
                         v += (JT_t)reinterpret_cast<const float *>(&slices[buf][w][jj])[o];
-                    jp[(size_t)o * a.npad + j] = v;
+                    jp[(size_t)o * len + (j - js)] = v;
                 }
             }
         }

@@ -215,18 +215,20 @@ def test_symmetric_engine_refused_where_not_built():
 
 def test_symmetric_workspace_size():
     """The symmetric engine's scratch: i-side partials per work-item segment plus the
-    j-side sums of every block row but the last, FP64 (PLAIN: FP32)."""
+    j-side sums of every block row but the last, each row only for the particles after
+    it, FP64 (PLAIN: FP32)."""
     o = _lib.nbody_opts_default()
     o.symmetric, o.ipl, o.jtile, o.nseg = 2, 1, 128, 4
     n = 5000  # block rows of 512: 10 rows, npad 5120; row 0 has 36 tiles -> 9 per item
-    rows, npad, segs = 9, 5120, 4
+    nb, bi, npad, segs = 10, 512, 5120, 4
+    jwords = 4 * bi * nb * (nb - 1) // 2  # rows of 9, 8, ..., 1 blocks of bi
     # (the FP64-position path adds FP32 positions and the centre partials)
     extra = 3 * 4 * n + 8192 + 768
-    want = segs * 8 * npad * 4 + rows * 4 * npad * 8
+    want = segs * 8 * npad * 4 + jwords * 8
     got = _lib.nbody_workspace_size(n, o)
     assert want <= got <= want + extra
     o.precision = _lib.NBODY_PLAIN
-    want = segs * 4 * npad * 4 + rows * 4 * npad * 4
+    want = segs * 4 * npad * 4 + jwords * 4
     got = _lib.nbody_workspace_size(n, o)
     assert want <= got <= want + extra
 
