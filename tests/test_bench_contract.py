@@ -96,3 +96,10 @@ def test_warm_up_fills_its_time_budget_or_the_given_count():
     calls.clear()
     assert bench.warm_up(FakeTorch, call, 3) == 3 and len(calls) == 3
     assert bench.warm_up(FakeTorch, call, 0) == 0
+
+
+def test_symmetric_flag_is_parsed_and_off_by_default():
+    # The default line measures the library's default engine; --symmetric asks for the
+    # opt-in symmetric engine on the N = 131072 workload.
+    assert bench.parse([]).symmetric is False
+    assert bench.parse(["--symmetric"]).symmetric is True
