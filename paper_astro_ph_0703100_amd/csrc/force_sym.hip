@@ -96,7 +96,7 @@ nbody_status launch_pair_sym(const TileCfg &cfg, int precision, bool with_pot,
     if (!fn) return set_error(NBODY_EUNSUPPORTED, "no symmetric-engine kernel for this shape");
     if (a.n <= 0) return NBODY_OK;
     const int bi = 64 * kSymWaves * cfg.ipl;
-    const size_t ibytes = align_up((size_t)cfg.nseg * partial_words(precision) * (size_t)cfg.npad * 4, 256);
+    const size_t ibytes = sym_ipart_bytes(cfg, precision);  // the j-side sums follow
     SymArgs sa{a.x, a.y, a.z, a.m, a.n, a.eps2, cfg.segt, cfg.nb, cfg.nseg, cfg.npad,
                a.part, static_cast<char *>(a.part) + ibytes};
     hipLaunchKernelGGL(fn, dim3(cfg.nitems), dim3(64 * kSymWaves), 0, s, sa);
