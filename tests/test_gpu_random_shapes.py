@@ -222,3 +222,34 @@ def test_split_vjp(k):
     tol = 1e-4 if c["precision"] == "plain" else 1e-5
     assert rel_errors(gx.cpu().numpy().T, rx)["rel_rms"] <= tol, c
     assert scaled_max(gm.cpu().numpy(), rm) <= tol, c
+
+
+def draw_sym(rng):
+    return {"n": int(rng.integers(2, 9000)), "ipl": int(rng.choice([1, 2, 4])),
+            "jtile": int(rng.choice([64, 128])), "nseg": int(rng.integers(0, 40)),
+            "precision": str(rng.choice(["comp", "fp64red", "plain"])),
+            "eps": float(np.float32(10 ** rng.uniform(-3, -1)))}
+
+
+SYM_CASES = [draw_sym(np.random.default_rng(15000 + k)) for k in range(16)]
+
+
+@pytest.mark.parametrize("k", range(len(SYM_CASES)))
+def test_sym_force(k):
+    # The symmetric engine (each unordered pair once): a potential term passes through at
+    # most 16 ipl + 2 FP32 additions on the j side (a record load of 16 steps, four loads
+    # per chunk), 63 on the i side (a 64-record chunk), then FP64 or a two-sum; plain FP32
+    # stays below n + 1024.
+    c = SYM_CASES[k]
+    x, _, m = sphere(c["n"], 16000 + k)
+    shape = dict(ipl=c["ipl"], jtile=c["jtile"], nseg=c["nseg"], symmetric=2)
+    acc, pot = api.force(t32(x), torch.from_numpy(m.astype(np.float32)).to(DEV), c["eps"],
+                         precision=c["precision"], **shape)
+    torch.cuda.synchronize()
+    ra, rp = oracle.force_all(x, m, c["eps"])
+    ea = rel_errors(acc.cpu().numpy().T, ra)
+    adds = 127 if c["precision"] != "plain" else c["n"] + 1024
+    bound = (bounds.C_POT + adds) * U * np.abs(rp)
+    assert ea["rel_rms"] <= TOL[c["precision"]], (c, ea)
+    perr = np.abs(pot.cpu().numpy() - rp)
+    assert np.all(perr <= bound), (c, float((perr / bound).max()))
