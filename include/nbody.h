@@ -168,10 +168,11 @@ NBODY_API nbody_status nbody_force_f64(int64_t n, const double *pos64, const flo
  * harnesses that forbid hipMalloc.  It calls no hipMalloc, hipFree or allocating
  * library routine.  The grid engine's segment partial sums go to a static device
  * array of NBODY_NOALLOC_SCRATCH_BYTES that every GPU the library runs on holds until
- * the process ends; the split engine needs none.  If the partial sums of the chosen
- * shape do not fit, fewer j-segments are used (unless opts->nseg is set); a size or
- * shape whose partial sums exceed the array even then returns NBODY_EINVAL with the
- * bytes it would need.  opts->workspace must be NULL.  All calls on one GPU share its
+ * the process ends; the split engine needs none, the symmetric engine's j-side sums
+ * share it.  If the partial sums of the chosen shape do not fit, a tuned symmetric
+ * shape gives way to the grid engine and fewer j-segments are used (unless
+ * opts->symmetric or opts->nseg is set); a size or shape whose partial sums exceed the
+ * array even then returns NBODY_EINVAL with the bytes it would need.  opts->workspace must be NULL.  All calls on one GPU share its
  * array: calls that overlap in time on one GPU (several streams, several host
  * threads) race and give wrong results; calls on one stream are ordered and safe.
  * Nothing in the array needs clearing between calls (every partial sum is written
