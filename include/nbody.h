@@ -171,7 +171,7 @@ NBODY_API nbody_status nbody_force_f64(int64_t n, const double *pos64, const flo
  * the process ends; the split engine needs none, the symmetric engine's j-side sums
  * share it.  If the partial sums of the chosen shape do not fit, a tuned symmetric
  * shape gives way to the grid engine and fewer j-segments are used (unless
- * opts->symmetric or opts->nseg is set); a size or shape whose partial sums exceed the
+ * opts->symmetric is 2 or opts->nseg is set); a size or shape whose partial sums exceed the
  * array even then returns NBODY_EINVAL with the bytes it would need.  opts->workspace must be NULL.  All calls on one GPU share its
  * array: calls that overlap in time on one GPU (several streams, several host
  * threads) race and give wrong results; calls on one stream are ordered and safe.
